@@ -1,0 +1,180 @@
+/*
+ * efe.h -- C ABI of the MI355X enriched-finite-element (EFE) eigensolver.
+ *
+ * The library solves the generalized Kohn-Sham eigenproblem H^E x = eps M^E x
+ * of the orthogonalized EFE basis (Sec. II.B, Eqs. lineigensolveghep,
+ * Discrete_Eig_Gen_H, Discrete_Eig_Gen_M) by residual Chebyshev-filtered
+ * subspace iteration (Sec. III.B, Eqs. ChebyRecur, residual, residualapprox)
+ * followed by Rayleigh-Ritz (Eq. projectedKSEig), and runs the SCF pieces
+ * around it (Sec. II.A, III.C).  All compute runs in HIP kernels on the GPU
+ * selected when the context is created.
+ *
+ * Conventions shared by every entry point
+ *   Blocks of vectors are device arrays, row-major, one row per DoF and the
+ *   vectors of a row contiguous ("node-major"): element (r, j) at ptr[r*ld+j],
+ *   ld >= ncols.  Row order: the (ncell*p+1)^3 CFE nodes of the full grid
+ *   first (node (i,j,k) -> i + n1x*(j + n1y*k)), boundary nodes included and
+ *   held at zero (homogeneous Dirichlet), then the enrichment rows, atom after
+ *   atom, n_f = (lmax+1)^2 functions per atom (Sec. II.B: M = n_h + sum n_I).
+ *   The caller owns every block and device array it passes; the library owns
+ *   its context and workspaces and frees them in efe_destroy.
+ *   All work is ordered on the stream given to efe_setup_mesh; calls that
+ *   return values in host memory synchronize that stream.
+ *   Errors: every call returns an efe_status; arguments are checked before any
+ *   launch; the message of the last failure is kept for efe_last_error.
+ *   One context per host thread.
+ */
+#ifndef EFE_H
+#define EFE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t efe_status;
+#define EFE_OK        0
+#define EFE_EINVAL   -1   /* bad argument (null pointer, size, range)       */
+#define EFE_ENOMEM   -2   /* device allocation failed                        */
+#define EFE_EHIP     -3   /* a HIP runtime call failed                       */
+#define EFE_ENOTCONV -4   /* an iteration did not converge                    */
+#define EFE_ENUMERIC -5   /* numerical breakdown (Cholesky, non-finite data) */
+#define EFE_ESTATE   -6   /* call out of order (e.g. no potential set)       */
+
+/* Precision of the filter's cell GEMMs and projector updates (Sec. III.B runs
+ * in FP64; FP32 and BF16 keep FP64 eigen-residual, output and Rayleigh-Ritz). */
+#define EFE_FP64 0
+#define EFE_FP32 1
+#define EFE_BF16 2
+
+#define EFE_FILTER_RESIDUAL 0   /* Eqs. residual, residualapprox             */
+#define EFE_FILTER_STANDARD 1   /* Eq. ChebyRecur on (M~^E)^-1 H^E           */
+
+typedef struct efe_ctx efe_ctx;
+
+/* Uniform hexahedral mesh of spectral elements of order p (GLL nodes) on the
+ * box [lo, hi]; nq Gauss points per axis for integrals with a potential, a
+ * gradient, an enrichment function or a projector (Sec. III.A). */
+typedef struct {
+  double lo[3], hi[3];
+  int32_t ncell[3];
+  int32_t p;    /* 1 <= p <= 7 */
+  int32_t nq;   /* 1 <= nq <= 7 */
+} efe_mesh_desc;
+
+/* Atoms and the synthetic pseudopotential / enrichment parameters.
+ *   local part   v(r) = -Z erf(r/loc_rc)/r + loc_amp exp(-(r/loc_rg)^2)
+ *   projector    beta(r) = (pi w^2)^(-3/4) exp(-r^2/(2 w^2)), r < kb_rcut,
+ *                one per atom with coupling kb_D (kb_width <= 0: none)
+ *   enrichment   S_lm(x-R) exp(-enr_alpha r^2) h(r), l <= enr_lmax, smooth
+ *                cutoff h ending at enr_rcut with smoothness enr_t
+ *                (Eq. eqnCutoffProperties); enr_lmax < 0: plain CFE
+ *   rho_alpha    exponent of the Gaussian isolated-atom density (Sec. III.C)
+ * xyz and Z are host arrays read during efe_setup_mesh only. */
+typedef struct {
+  int32_t natoms;
+  const double *xyz;
+  const double *Z;
+  double loc_rc, loc_amp, loc_rg;
+  double kb_width, kb_D, kb_rcut;
+  int32_t enr_lmax;
+  double enr_alpha, enr_rcut, enr_t;
+  double rho_alpha;
+} efe_system_desc;
+
+/* Build the mesh tables, the enrichment and projector data and the overlap
+ * blocks (Sec. II.B, III.A): lumped CFE mass, C = b diag(m)^-1, M^ee and the
+ * inverses of its atom-diagonal blocks (Eq. MEInvApprox).  `stream` is a
+ * hipStream_t (NULL: default stream).  On success *out owns device memory. */
+efe_status efe_setup_mesh(const efe_mesh_desc *mesh, const efe_system_desc *sys,
+                          void *stream, efe_ctx **out);
+
+/* sizes[0..7] = rows, n_nodes, n_dof (interior nodes + enrichment), n_enr,
+ * n_cells, n_qpts (n_cells * nq^3), natoms, nloc ((p+1)^3).  Host array. */
+efe_status efe_get_sizes(const efe_ctx *ctx, int64_t *sizes);
+
+/* Integer mesh tables in host memory (any pointer may be NULL):
+ * cell_to_global[n_cells*nloc], colour_order[n_cells] (cells sorted by colour
+ * (cx&1)+2(cy&1)+4(cz&1), then id), colour_offsets[9], boundary[n_nodes]. */
+efe_status efe_get_tables(const efe_ctx *ctx, int32_t *cell_to_global, int32_t *colour_order,
+                          int32_t *colour_offsets, uint8_t *boundary);
+
+/* Per-atom support cells (which = 0: enrichment, radius enr_rcut; 1: projector,
+ * radius kb_rcut).  A cell belongs when its box distance to the atom is below
+ * the radius.  *npairs receives the total; ptr[natoms+1] and cells[*npairs]
+ * (ascending per atom) are filled when non-NULL.  Host arrays. */
+efe_status efe_get_support(const efe_ctx *ctx, int32_t which, int64_t *npairs,
+                           int32_t *ptr, int32_t *cells);
+
+/* vq[n_qpts] (device) = sum over atoms of the local pseudopotential at the
+ * Gauss points, cell-major (Sec. II.A, Eq. Eel). */
+efe_status efe_local_potential(efe_ctx *ctx, double *vq);
+
+/* Set the local Kohn-Sham potential at the Gauss points (device, n_qpts) and
+ * rebuild the potential-dependent blocks: per-cell Hamiltonians
+ * 1/2 K_cell + V_cell, the enrichment coupling B and H^phiphi (Eq. KS,
+ * Discrete_Eig_Gen_H).  `precisions` is a bit mask of (1 << EFE_FP32) and
+ * (1 << EFE_BF16) for the reduced-precision cell matrices to keep as well. */
+efe_status efe_set_potential(efe_ctx *ctx, const double *vq, int32_t precisions);
+
+/* Y = H^E X for ncols vectors (device blocks, rows x ld). */
+efe_status efe_apply_H(efe_ctx *ctx, const double *X, double *Y, int32_t ncols, int64_t ld);
+/* Y = M^E X (exact overlap: diag(m) on CFE rows, M^ee on enrichment rows). */
+efe_status efe_apply_M(efe_ctx *ctx, const double *X, double *Y, int32_t ncols, int64_t ld);
+/* Y = (M~^E)^-1 X (Eq. MEInvApprox). */
+efe_status efe_apply_Minv_approx(efe_ctx *ctx, const double *X, double *Y, int32_t ncols,
+                                 int64_t ld);
+
+/* Upper bound of the spectrum of (M~^E)^-1 H^E by `steps` Lanczos steps in
+ * the M~ inner product from the device start vector v0 (rows):
+ * theta_max(T) + |beta_last|.  Result in host memory. */
+efe_status efe_spectrum_upper_bound(efe_ctx *ctx, const double *v0, int32_t steps,
+                                    double *b_out);
+
+typedef struct {
+  int32_t degree;     /* m >= 1 */
+  double a, b, a_min; /* unwanted interval (a, b); a_min <= lowest eigenvalue < a */
+  int32_t mode;       /* EFE_FILTER_RESIDUAL or EFE_FILTER_STANDARD */
+  int32_t prec;       /* EFE_FP64, EFE_FP32, EFE_BF16 (cell GEMMs, projectors) */
+} efe_cheb_params;
+
+/* Chebyshev filter of ncols vectors in place (Sec. III.B).  Residual mode
+ * needs the Ritz values `lambda` (device, ncols) paired with V:
+ *   G = H V - M V Lambda, Z_1 = (s1/e) G,
+ *   Z_k = (2 s_k/e) H M~^-1 Z_{k-1} - (2 c s_k/e) Z_{k-1} - s_{k-1} s_k Z_{k-2}
+ *         + (2 s_k/e) G C_{k-1}(Lambda),
+ *   V <- M~^-1 Z_m + V C_m(Lambda).
+ * Standard mode ignores lambda and applies C_m((M~^E)^-1 H^E) to V. */
+efe_status efe_cheb_filter(efe_ctx *ctx, double *V, const double *lambda, int32_t ncols,
+                           int64_t ld, const efe_cheb_params *prm);
+
+/* Rayleigh-Ritz in FP64 (Eq. projectedKSEig): S = V^T M V, Hp = V^T H V,
+ * S = L L^T, L^-1 Hp L^-T = Q Lambda Q^T (Jacobi), V <- V L^-T Q.
+ * lambda (device, ncols) ascending; resnorm (device, ncols, may be NULL)
+ * = ||H v_j - lambda_j M v_j||_2.  Boundary rows of V are set to zero.
+ * Returns EFE_ENUMERIC if S is not positive definite. */
+efe_status efe_rayleigh_ritz(efe_ctx *ctx, double *V, int32_t ncols, int64_t ld,
+                             double *lambda, double *resnorm);
+
+/* Kernel timing.  enable != 0 clears earlier records and starts recording HIP
+ * events on the context's stream around the tracked launches; 0 stops.
+ * efe_timing_get returns, for a kernel class, the number of recorded launches
+ * and their summed duration in milliseconds (synchronizes the stream):
+ *   0 one colour pass of the cell GEMM   1 pre pass of an H apply
+ *   2 enrichment rows of an H apply      3 residual recurrence update
+ *   4 whole H apply                      5 whole Rayleigh-Ritz */
+efe_status efe_timing(efe_ctx *ctx, int32_t enable);
+efe_status efe_timing_get(efe_ctx *ctx, int32_t which, int64_t *launches, double *total_ms);
+
+/* Message of the last failure on this context ("" if none); with ctx == NULL
+ * the message of the last failed efe_setup_mesh on the calling thread. */
+const char *efe_last_error(const efe_ctx *ctx);
+
+/* Free the context and everything it owns (NULL is ignored). */
+void efe_destroy(efe_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EFE_H */

@@ -142,7 +142,7 @@ def lanczos_upper_bound(apply_H, apply_Mt, apply_Mt_inv, v0, k=20):
         beta_prev = beta
     T = np.diag(alphas) + np.diag(betas[:-1], 1) + np.diag(betas[:-1], -1)
     theta = np.linalg.eigvalsh(T)
-    return float(theta[-1] + abs(betas[-1])), np.array(alphas), np.array(betas)
+    return float(theta[-1] + abs(betas[-1])), float(theta[-1]), np.array(betas)
 
 
 # ---------------------------------------------------------------- driver

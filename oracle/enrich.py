@@ -361,7 +361,7 @@ class EFESystem:
         n = self.n_nodes
         Y = np.zeros_like(X)
         Y[:n] = self.minv.reshape((-1,) + (1,) * (X.ndim - 1)) * X[:n]
-        for I in range(self.natoms):
+        for I in range(self.natoms if self.nf else 0):
             s = slice(n + I * self.nf, n + (I + 1) * self.nf)
             Y[s] = self.Mee_blocks_inv[I] @ X[s]
         return Y
@@ -384,10 +384,25 @@ class EFESystem:
         n = self.n_nodes
         Y = np.zeros_like(X)
         Y[:n] = (self.m * self.intr).reshape((-1,) + (1,) * (X.ndim - 1)) * X[:n]
-        for I in range(self.natoms):
+        for I in range(self.natoms if self.nf else 0):
             s = slice(n + I * self.nf, n + (I + 1) * self.nf)
             Y[s] = self.Mee[s.start - n:s.stop - n, s.start - n:s.stop - n] @ X[s]
         return Y
+
+    def tilde_condition(self):
+        """Round-off amplification of (M~^E)^-1: max over atoms of
+        ||M^phiphi_II|| / lambda_min(M^ee_II) (1 without enrichment).  M^ee is
+        a difference of two terms of the size of M^phiphi, so its entries carry
+        absolute round-off of that size; when the enrichment lies close to the
+        CFE space M^ee is small and the relative error of its inverse grows by
+        this ratio."""
+        if not self.nf:
+            return 1.0
+        out = 1.0
+        for I in range(self.natoms):
+            s = slice(I * self.nf, (I + 1) * self.nf)
+            out = max(out, np.linalg.norm(self.Mpp[s, s], 2) / np.linalg.eigvalsh(self.Mee[s, s])[0])
+        return out
 
     # ------------------------------------------------------- dense forms
     def active(self):

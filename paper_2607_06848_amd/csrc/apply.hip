@@ -1,0 +1,388 @@
+// Application of the EFE Hamiltonian H^E = T^T Hhat T (Sec. II.B, Eq.
+// Discrete_Eig_Gen_H), the exact overlap M^E and its approximate inverse
+// (Eq. MEInvApprox) to a block of node-major vectors.
+//
+// With T = [[I, -C^T], [0, I]] the apply of Y = H^E X runs as
+//   pre        Xh = s X^C - C^T X^E,  Y^C = B^T X^E       (node-major lists)
+//   project    W  = D (P^C Xh + P^phi X^E)                 (projector rows)
+//   cell       Y^C += sum_c P_c^T H_c P_c Xh               (MFMA cell GEMM,
+//              eight colour passes, no two cells of a pass share a node)
+//   expand     Y^C += P^C^T W
+//   enrichment Y^E  = H^phiphi X^E + P^phi^T W + B Xh - C Y^C
+// where s = 1, or 1/m when the caller folds the CFE part of (M~^E)^-1 in.
+#include "efe_device.h"
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// ------------------------------------------------------------------ pre
+__global__ __launch_bounds__(256) void k_pre(int64_t n_nodes, int ncols, const double *__restrict__ XC,
+                                             int64_t ldx, const double *__restrict__ scale,
+                                             const double *__restrict__ minv,
+                                             const double *__restrict__ XE, int64_t lde,
+                                             const int32_t *__restrict__ nm_ptr,
+                                             const int32_t *__restrict__ nm_atom,
+                                             const double *__restrict__ C_nm,
+                                             const double *__restrict__ B_nm, int nf,
+                                             double *__restrict__ Xh, int64_t ldh,
+                                             double *__restrict__ Y, int64_t ldy) {
+  const int64_t j = (int64_t)blockIdx.x * 4 + threadIdx.y;
+  if (j >= n_nodes) return;
+  const bool inner = minv[j] != 0.0;
+  const double s = scale ? scale[j] : 1.0;
+  const int32_t e0 = nm_ptr[j], e1 = nm_ptr[j + 1];
+  for (int col = threadIdx.x; col < ncols; col += 64) {
+    double xh = 0.0, y = 0.0;
+    if (inner) {
+      xh = s * XC[j * ldx + col];
+      for (int32_t e = e0; e < e1; ++e) {
+        const double *xe = XE + (int64_t)nm_atom[e] * nf * lde + col;
+        const double *cc = C_nm + (int64_t)e * nf;
+        const double *bb = B_nm + (int64_t)e * nf;
+        for (int k = 0; k < nf; ++k) {
+          const double v = xe[(int64_t)k * lde];
+          xh -= cc[k] * v;
+          y += bb[k] * v;
+        }
+      }
+    }
+    Xh[j * ldh + col] = xh;
+    Y[j * ldy + col] = y;
+  }
+}
+
+// ------------------------------------------------------------------ cell GEMM
+// One block = one cell of the current colour and NT columns.  The gathered
+// 16-row-padded block Xh_cell (KP x NT) sits in LDS; each wave streams the
+// pre-tiled cell matrix rows (one 512-byte operand load per MFMA k-step) and
+// accumulates 16 x NT output tiles with v_mfma_f64_16x16x4.  Results are
+// added to Y on interior nodes; cells of one colour share no node, so the
+// read-modify-write needs no atomics.  blockIdx -> (cell, tile) keeps all
+// column tiles of a cell on one XCD (blocks are dealt round-robin over 8).
+template <int NT>
+__global__ __launch_bounds__(256) void k_cell_f64(int ncells, int ntiles,
+                                                  const int32_t *__restrict__ cells,
+                                                  const int32_t *__restrict__ c2g, int nloc,
+                                                  int RB, int KS, const double *__restrict__ Ht,
+                                                  const double *__restrict__ Xh, int64_t ldx,
+                                                  double *__restrict__ Y, int64_t ldy,
+                                                  const double *__restrict__ minv, int ncols) {
+  extern __shared__ double Xs[];   // [KP][NT]
+  const int b = blockIdx.x;
+  const int xcd = b % 8, slot = b / 8;
+  const int ci = (slot / ntiles) * 8 + xcd;
+  const int tile = slot % ntiles;
+  if (ci >= ncells) return;
+  const int cell = cells[ci];
+  const int col0 = tile * NT;
+  const int KP = KS * 4;
+  const int32_t *g = c2g + (int64_t)cell * nloc;
+  for (int idx = threadIdx.x; idx < KP * NT; idx += 256) {
+    const int r = idx / NT, cc = idx % NT;
+    double v = 0.0;
+    if (r < nloc && col0 + cc < ncols) v = Xh[(int64_t)g[r] * ldx + col0 + cc];
+    Xs[idx] = v;
+  }
+  __syncthreads();
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int li = lane % 16, lk = lane / 16;
+  for (int rb = wave; rb < RB; rb += 4) {
+    v4d acc[NT / 16];
+    for (int cb = 0; cb < NT / 16; ++cb) acc[cb] = (v4d){0.0, 0.0, 0.0, 0.0};
+    const double *hp = Ht + (((int64_t)cell * RB + rb) * KS) * 64 + lane;
+    double a_next = hp[0];
+    for (int ks = 0; ks < KS; ++ks) {
+      const double a = a_next;
+      if (ks + 1 < KS) a_next = hp[(int64_t)(ks + 1) * 64];
+      const double *xr = Xs + (ks * 4 + lk) * NT + li;
+#pragma unroll
+      for (int cb = 0; cb < NT / 16; ++cb)
+        acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, xr[cb * 16], acc[cb], 0, 0, 0);
+    }
+    // FP64 16x16x4 accumulator: register v of lane l holds row 4 v + l/16
+    for (int v = 0; v < 4; ++v) {
+      const int row = rb * 16 + 4 * v + lk;
+      if (row >= nloc) continue;
+      const int64_t node = g[row];
+      if (minv[node] == 0.0) continue;
+#pragma unroll
+      for (int cb = 0; cb < NT / 16; ++cb) {
+        const int col = col0 + cb * 16 + li;
+        if (col < ncols) Y[node * ldy + col] += acc[cb][v];
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ projectors
+__global__ __launch_bounds__(256) void k_kb_project(int ncols, const int32_t *__restrict__ kbnode_ptr,
+                                                    const int32_t *__restrict__ kbnode,
+                                                    const double *__restrict__ Pc,
+                                                    const double *__restrict__ Xh, int64_t ldh,
+                                                    const double *__restrict__ Pphi, int64_t n_enr,
+                                                    const double *__restrict__ XE, int64_t lde,
+                                                    const double *__restrict__ D,
+                                                    double *__restrict__ W) {
+  __shared__ double red[4][64];
+  const int I = blockIdx.x;
+  const int col = blockIdx.y * 64 + threadIdx.x;
+  double acc = 0.0;
+  if (col < ncols) {
+    for (int32_t s = kbnode_ptr[I] + threadIdx.y; s < kbnode_ptr[I + 1]; s += 4)
+      acc += Pc[s] * Xh[(int64_t)kbnode[s] * ldh + col];
+    for (int64_t f = threadIdx.y; f < n_enr; f += 4)
+      acc += Pphi[(int64_t)I * n_enr + f] * XE[f * lde + col];
+  }
+  red[threadIdx.y][threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.y == 0 && col < ncols)
+    W[(int64_t)I * ncols + col] =
+        D[I] * (red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x]);
+}
+
+__global__ __launch_bounds__(256) void k_kb_expand(int64_t n_nodes, int ncols,
+                                                   const int32_t *__restrict__ kbnm_ptr,
+                                                   const int32_t *__restrict__ kbnm_atom,
+                                                   const double *__restrict__ Pc_nm,
+                                                   const double *__restrict__ W,
+                                                   double *__restrict__ Y, int64_t ldy) {
+  const int64_t j = (int64_t)blockIdx.x * 4 + threadIdx.y;
+  if (j >= n_nodes) return;
+  const int32_t e0 = kbnm_ptr[j], e1 = kbnm_ptr[j + 1];
+  if (e0 == e1) return;
+  for (int col = threadIdx.x; col < ncols; col += 64) {
+    double acc = 0.0;
+    for (int32_t e = e0; e < e1; ++e) acc += Pc_nm[e] * W[(int64_t)kbnm_atom[e] * ncols + col];
+    Y[j * ldy + col] += acc;
+  }
+}
+
+// Y^E[I k] += sum over the atom's support nodes of B[s][k] Xh[node] - C[s][k] Y[node]
+__global__ __launch_bounds__(256) void k_enr_post(int nf, int ncols, int chunk,
+                                                  const int32_t *__restrict__ snode_ptr,
+                                                  const int32_t *__restrict__ snode,
+                                                  const double *__restrict__ B_am,
+                                                  const double *__restrict__ C_am,
+                                                  const double *__restrict__ Xh, int64_t ldh,
+                                                  const double *__restrict__ Y, int64_t ldy,
+                                                  double *__restrict__ YE, int64_t lde) {
+  __shared__ double red[4][9][64];
+  const int I = blockIdx.x;
+  const int32_t s0 = snode_ptr[I] + blockIdx.y * chunk;
+  const int32_t s1 = min(snode_ptr[I + 1], s0 + chunk);
+  if (s0 >= s1) return;
+  const int col = blockIdx.z * 64 + threadIdx.x;
+  double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  if (col < ncols) {
+    for (int32_t s = s0 + threadIdx.y; s < s1; s += 4) {
+      const int64_t node = snode[s];
+      const double xh = Xh[node * ldh + col], y = Y[node * ldy + col];
+      const double *bb = B_am + (int64_t)s * nf, *cc = C_am + (int64_t)s * nf;
+      for (int k = 0; k < nf; ++k) acc[k] += bb[k] * xh - cc[k] * y;
+    }
+  }
+  for (int k = 0; k < nf; ++k) red[threadIdx.y][k][threadIdx.x] = acc[k];
+  __syncthreads();
+  if (threadIdx.y == 0 && col < ncols)
+    for (int k = 0; k < nf; ++k)
+      atomicAdd(&YE[(int64_t)(I * nf + k) * lde + col],
+                red[0][k][threadIdx.x] + red[1][k][threadIdx.x] + red[2][k][threadIdx.x] +
+                    red[3][k][threadIdx.x]);
+}
+
+// ------------------------------------------------------------------ overlap
+// CFE rows: Y = w X (w = m or 1/m, zero on the boundary)
+__global__ void k_rowscale(int64_t n, int ncols, const double *__restrict__ w,
+                           const double *__restrict__ X, int64_t ldx, double *__restrict__ Y,
+                           int64_t ldy) {
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= n * ncols) return;
+  const int64_t r = idx / ncols, c = idx % ncols;
+  Y[r * ldy + c] = w[r] * X[r * ldx + c];
+}
+
+// Enrichment rows: Y_I = inv_I X_I for each atom block
+__global__ void k_enr_block_apply(int natoms, int nf, int ncols, const double *__restrict__ inv,
+                                  const double *__restrict__ X, int64_t ldx,
+                                  double *__restrict__ Y, int64_t ldy) {
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)natoms * nf * ncols) return;
+  const int c = idx % ncols;
+  const int64_t f = idx / ncols;
+  const int I = f / nf, k = f % nf;
+  const double *a = inv + ((int64_t)I * nf + k) * nf;
+  double acc = 0.0;
+  for (int l = 0; l < nf; ++l) acc += a[l] * X[((int64_t)I * nf + l) * ldx + c];
+  Y[f * ldy + c] = acc;
+}
+
+// ------------------------------------------------------------------ launchers
+// Column tile of the FP64 cell GEMM: 32 columns need 88 KB of LDS at p = 6,
+// which needs the dynamic-LDS limit raised above 64 KB; 16 otherwise.
+static int cell_nt64(efe_ctx *c) {
+  if (c->cell_nt64 == 0) {
+    const size_t shm32 = (size_t)c->KP * 32 * 8;
+    c->cell_nt64 = 16;
+    if (shm32 <= 64 * 1024) {
+      c->cell_nt64 = 32;
+    } else if (hipFuncSetAttribute((const void *)k_cell_f64<32>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)shm32) == hipSuccess) {
+      c->cell_nt64 = 32;
+    } else {
+      (void)hipGetLastError();
+    }
+  }
+  return c->cell_nt64;
+}
+
+efe_status efe_apply_H_internal(efe_ctx *c, const double *XC, int64_t ldx, const double *scale,
+                                const double *XE, int64_t lde, double *Y, int64_t ldy, int ncols,
+                                int prec) {
+  if (!c->have_potential) EFE_FAIL(c, EFE_ESTATE, "no potential set");
+  if (ncols <= 0) return EFE_OK;
+  (void)prec;
+  efe_status s;
+  double *Xh, *W = nullptr;
+  const int64_t ldh = ncols;
+  if ((s = efe_ws(c, 0, (size_t)c->n_nodes * ldh * 8, (void **)&Xh))) return s;
+  if (c->nproj && (s = efe_ws(c, 1, (size_t)c->nproj * ncols * 8, (void **)&W))) return s;
+  const int nf = c->nf;
+  double *YE = Y + c->n_nodes * ldy;
+  const int t_apply = efe_timer_begin(c, EFE_T_APPLY);
+  // pre: Xh and Y^C = B^T X^E
+  {
+    dim3 blk(64, 4);
+    const int t = efe_timer_begin(c, EFE_T_PRE);
+    k_pre<<<cdiv(c->n_nodes, 4), blk, 0, c->stream>>>(
+        c->n_nodes, ncols, XC, ldx, scale, c->d_minv, XE, lde, c->d_nm_ptr, c->d_nm_atom, c->d_C_nm,
+        c->d_B_nm, nf, Xh, ldh, Y, ldy);
+    efe_timer_end(c, EFE_T_PRE, t);
+  }
+  // projector coefficients
+  if (c->nproj) {
+    dim3 blk(64, 4), grd(c->nproj, cdiv(ncols, 64));
+    k_kb_project<<<grd, blk, 0, c->stream>>>(ncols, c->d_kbnode_ptr, c->d_kbnode, c->d_Pc_am, Xh,
+                                             ldh, c->d_Pphi, c->n_enr, XE, lde, c->d_D, W);
+  }
+  // cell GEMM, colour by colour
+  {
+    const int NT = cell_nt64(c);
+    const int ntiles = (int)cdiv(ncols, NT);
+    const size_t shm = (size_t)c->KP * NT * 8;
+    for (int col = 0; col < 8; ++col) {
+      const int nc = c->colour_offsets[col + 1] - c->colour_offsets[col];
+      if (nc == 0) continue;
+      const int64_t nblk = cdiv(nc, 8) * 8 * ntiles;
+      const int t = efe_timer_begin(c, EFE_T_CELL);
+      if (NT == 32)
+        k_cell_f64<32><<<nblk, 256, shm, c->stream>>>(
+            nc, ntiles, c->d_colour_order + c->colour_offsets[col], c->d_c2g, c->nloc, c->RB,
+            c->KS, c->d_Htile64, Xh, ldh, Y, ldy, c->d_minv, ncols);
+      else
+        k_cell_f64<16><<<nblk, 256, shm, c->stream>>>(
+            nc, ntiles, c->d_colour_order + c->colour_offsets[col], c->d_c2g, c->nloc, c->RB,
+            c->KS, c->d_Htile64, Xh, ldh, Y, ldy, c->d_minv, ncols);
+      efe_timer_end(c, EFE_T_CELL, t);
+    }
+  }
+  if (c->nproj) {
+    dim3 blk(64, 4);
+    k_kb_expand<<<cdiv(c->n_nodes, 4), blk, 0, c->stream>>>(c->n_nodes, ncols, c->d_kbnm_ptr,
+                                                            c->d_kbnm_atom, c->d_Pc_nm, W, Y, ldy);
+  }
+  // enrichment rows
+  const int t_post = efe_timer_begin(c, EFE_T_POST);
+  if (c->n_enr) {
+    if ((s = efe_gemm(c, false, false, c->n_enr, ncols, c->n_enr, 1.0, c->d_Hpp, c->n_enr, XE, lde,
+                      0.0, YE, ldy)))
+      return s;
+    if (c->nproj &&
+        (s = efe_gemm(c, true, false, c->n_enr, ncols, c->nproj, 1.0, c->d_Pphi, c->n_enr, W, ncols,
+                      1.0, YE, ldy)))
+      return s;
+    int maxs = 0;
+    for (int I = 0; I < c->natoms; ++I)
+      maxs = std::max(maxs, c->snode_ptr_h[I + 1] - c->snode_ptr_h[I]);
+    const int chunk = 1024;
+    dim3 blk(64, 4), grd(c->natoms, cdiv(maxs, chunk), cdiv(ncols, 64));
+    k_enr_post<<<grd, blk, 0, c->stream>>>(nf, ncols, chunk, c->d_snode_ptr, c->d_snode,
+                                           c->d_B_am, c->d_C_am, Xh, ldh, Y, ldy, YE, ldy);
+  }
+  efe_timer_end(c, EFE_T_POST, t_post);
+  efe_timer_end(c, EFE_T_APPLY, t_apply);
+  HIPCHK(c, hipGetLastError());
+  return EFE_OK;
+}
+
+efe_status efe_apply_M_internal(efe_ctx *c, const double *X, int64_t ldx, double *Y, int64_t ldy,
+                                int ncols) {
+  if (ncols <= 0) return EFE_OK;
+  k_rowscale<<<cdiv(c->n_nodes * ncols, 256), 256, 0, c->stream>>>(c->n_nodes, ncols, c->d_m_int,
+                                                                   X, ldx, Y, ldy);
+  HIPCHK(c, hipGetLastError());
+  if (c->n_enr)
+    return efe_gemm(c, false, false, c->n_enr, ncols, c->n_enr, 1.0, c->d_Mee, c->n_enr,
+                    X + c->n_nodes * ldx, ldx, 0.0, Y + c->n_nodes * ldy, ldy);
+  return EFE_OK;
+}
+
+efe_status efe_enr_block_inv(efe_ctx *c, const double *XE, int64_t ldx, double *YE, int64_t ldy,
+                             int ncols) {
+  if (!c->n_enr || ncols <= 0) return EFE_OK;
+  const int64_t n = c->n_enr * ncols;
+  k_enr_block_apply<<<cdiv(n, 256), 256, 0, c->stream>>>(c->natoms, c->nf, ncols, c->d_Mee_inv, XE,
+                                                         ldx, YE, ldy);
+  HIPCHK(c, hipGetLastError());
+  return EFE_OK;
+}
+
+efe_status efe_apply_Minv_internal(efe_ctx *c, const double *X, int64_t ldx, double *Y,
+                                   int64_t ldy, int ncols) {
+  if (ncols <= 0) return EFE_OK;
+  k_rowscale<<<cdiv(c->n_nodes * ncols, 256), 256, 0, c->stream>>>(c->n_nodes, ncols, c->d_minv, X,
+                                                                   ldx, Y, ldy);
+  HIPCHK(c, hipGetLastError());
+  return efe_enr_block_inv(c, X + c->n_nodes * ldx, ldx, Y + c->n_nodes * ldy, ldy, ncols);
+}
+
+// ------------------------------------------------------------------ C ABI
+static efe_status check_block(efe_ctx *c, const void *X, const void *Y, int ncols, int64_t ld) {
+  if (!c) return EFE_EINVAL;
+  if (!X || !Y || ncols < 0 || ld < ncols || ld < 1) EFE_FAIL(c, EFE_EINVAL, "bad block arguments");
+  if (X == Y) EFE_FAIL(c, EFE_EINVAL, "input and output blocks must differ");
+  return EFE_OK;
+}
+
+extern "C" efe_status efe_local_potential(efe_ctx *c, double *vq) {
+  if (!c) return EFE_EINVAL;
+  if (!vq) EFE_FAIL(c, EFE_EINVAL, "null vq");
+  return efe_launch_local_potential(c, vq);
+}
+
+extern "C" efe_status efe_set_potential(efe_ctx *c, const double *vq, int32_t precisions) {
+  if (!c) return EFE_EINVAL;
+  if (!vq) EFE_FAIL(c, EFE_EINVAL, "null vq");
+  if (precisions & ~((1 << EFE_FP32) | (1 << EFE_BF16))) EFE_FAIL(c, EFE_EINVAL, "bad precision mask");
+  return efe_build_operators(c, vq, precisions);
+}
+
+extern "C" efe_status efe_apply_H(efe_ctx *c, const double *X, double *Y, int32_t ncols,
+                                  int64_t ld) {
+  efe_status s = check_block(c, X, Y, ncols, ld);
+  if (s) return s;
+  return efe_apply_H_internal(c, X, ld, nullptr, X + c->n_nodes * ld, ld, Y, ld, ncols, EFE_FP64);
+}
+
+extern "C" efe_status efe_apply_M(efe_ctx *c, const double *X, double *Y, int32_t ncols,
+                                  int64_t ld) {
+  efe_status s = check_block(c, X, Y, ncols, ld);
+  if (s) return s;
+  return efe_apply_M_internal(c, X, ld, Y, ld, ncols);
+}
+
+extern "C" efe_status efe_apply_Minv_approx(efe_ctx *c, const double *X, double *Y, int32_t ncols,
+                                            int64_t ld) {
+  efe_status s = check_block(c, X, Y, ncols, ld);
+  if (s) return s;
+  return efe_apply_Minv_internal(c, X, ld, Y, ld, ncols);
+}

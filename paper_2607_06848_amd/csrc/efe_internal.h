@@ -1,0 +1,167 @@
+// Internal declarations of the EFE library: context layout, error helpers
+// and the host-side launchers shared between translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/efe.h"
+
+#define EFE_MAXP 7
+#define EFE_MAXQ 7
+
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
+
+struct efe_ctx {
+  hipStream_t stream = nullptr;
+  int device = 0;
+  std::string err;
+
+  // ---------------------------------------------------------------- mesh
+  double lo[3], hi[3], h[3];
+  int ncell[3], p, P, nloc, nq, nqp;
+  int64_t n1[3];
+  int64_t n_nodes = 0, n_cells = 0, n_qpts = 0, rows = 0, n_dof = 0, n_enr = 0;
+  std::vector<int32_t> c2g, colour_order, boundary_i;
+  int32_t colour_offsets[9];
+  std::vector<uint8_t> boundary;
+
+  // ---------------------------------------------------------------- system
+  int natoms = 0, nf = 0, lmax = -1, nproj = 0;
+  std::vector<double> xyz, Z;
+  double loc_rc, loc_amp, loc_rg, kb_width, kb_D, kb_rcut, enr_alpha, enr_rcut, enr_t,
+      rho_alpha;
+
+  // support tables (host copies kept for efe_get_support)
+  std::vector<int32_t> enr_ptr, enr_cells, kb_ptr, kb_cells;
+
+  // ---------------------------------------------------------------- device
+  int32_t *d_c2g = nullptr, *d_colour_order = nullptr;
+  double *d_m = nullptr, *d_minv = nullptr;            // lumped mass, 1/m (0 on boundary)
+  double *d_m_int = nullptr;                           // lumped mass, 0 on boundary
+  double *d_N3 = nullptr, *d_G3 = nullptr;             // [nqp][nloc], [3][nqp][nloc]
+  double *d_W3 = nullptr, *d_K = nullptr;              // [nqp] (times Jacobian), [nloc][nloc]
+  double *d_xq1 = nullptr;                             // 1-D Gauss abscissae (nq)
+  double *d_xyz = nullptr, *d_Zs = nullptr;
+
+  // enrichment: (atom, cell) pairs sorted by atom then cell
+  int64_t npairs = 0;
+  int32_t *d_pair_atom = nullptr, *d_pair_cell = nullptr, *d_pair_lmap = nullptr;
+  int64_t n_snodes = 0;                                // sum over atoms of support nodes
+  int32_t *d_snode_ptr = nullptr, *d_snode = nullptr;
+  std::vector<int32_t> snode_ptr_h;
+  double *d_nu = nullptr;                              // normalization per function
+  double *d_b_am = nullptr, *d_C_am = nullptr, *d_Bkin_am = nullptr, *d_B_am = nullptr;
+  // node-major copy: per node the list of (atom, support-node index)
+  int64_t nnz_nm = 0;
+  int32_t *d_nm_ptr = nullptr, *d_nm_atom = nullptr, *d_nm_src = nullptr;
+  double *d_C_nm = nullptr, *d_B_nm = nullptr;
+  // (cell, I, J) triples of atoms sharing a support cell
+  int64_t ntrip = 0;
+  int32_t *d_trip = nullptr;
+  double *d_Mpp = nullptr, *d_Mee = nullptr, *d_Hpp_kin = nullptr, *d_Hpp = nullptr;
+  double *d_Mee_inv = nullptr;                         // [natoms][nf][nf]
+
+  // Kleinman-Bylander projectors (one per atom)
+  int64_t nkbpairs = 0;
+  int32_t *d_kbpair_atom = nullptr, *d_kbpair_cell = nullptr, *d_kbpair_lmap = nullptr;
+  int64_t n_kbnodes = 0;
+  int32_t *d_kbnode_ptr = nullptr, *d_kbnode = nullptr;
+  double *d_Pc_am = nullptr;
+  int64_t nnz_kbnm = 0;
+  int32_t *d_kbnm_ptr = nullptr, *d_kbnm_atom = nullptr, *d_kbnm_src = nullptr;
+  double *d_Pc_nm = nullptr;
+  int64_t nkbtrip = 0;
+  int32_t *d_kbtrip = nullptr;                         // (cell, I_kb, J_enr)
+  double *d_Pphi = nullptr, *d_D = nullptr;            // [nproj][n_enr], [nproj]
+
+  // potential-dependent operators
+  bool have_potential = false;
+  double *d_vq = nullptr;
+  double *d_Htile64 = nullptr;                         // MFMA-tiled cell Hamiltonians
+  float *d_Htile32 = nullptr;
+  uint16_t *d_Htile16 = nullptr;
+  int RB = 0, KS = 0, KP = 0;                          // tile geometry of the cell GEMM
+  int cell_nt64 = 0;                                   // column tile of the FP64 cell GEMM
+
+  // workspaces (grown on demand)
+  std::vector<DevBuf> ws;
+
+  // event timing (efe_timing)
+  bool timing = false;
+  std::vector<hipEvent_t> tev[6];   // start/stop pairs per kernel class
+  int64_t tused[6] = {0, 0, 0, 0, 0, 0};
+};
+
+// ------------------------------------------------------------------ helpers
+#define EFE_FAIL(ctx, code, msg)       \
+  do {                                 \
+    (ctx)->err = (msg);                \
+    return (code);                     \
+  } while (0)
+
+#define HIPCHK(ctx, call)                                                          \
+  do {                                                                             \
+    hipError_t e_ = (call);                                                        \
+    if (e_ != hipSuccess) {                                                        \
+      (ctx)->err = std::string(#call) + " failed: " + hipGetErrorString(e_);        \
+      return EFE_EHIP;                                                             \
+    }                                                                              \
+  } while (0)
+
+efe_status efe_alloc(efe_ctx *ctx, void **p, size_t bytes);
+// workspace slot `slot` of at least `bytes` bytes (kept across calls)
+efe_status efe_ws(efe_ctx *ctx, int slot, size_t bytes, void **p);
+
+static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ------------------------------------------------------------------ launchers
+// setup / operators (setup.hip)
+efe_status efe_build_reference(efe_ctx *ctx);
+efe_status efe_build_enrichment(efe_ctx *ctx);
+efe_status efe_build_operators(efe_ctx *ctx, const double *vq, int precisions);
+efe_status efe_launch_local_potential(efe_ctx *ctx, double *vq);
+
+// linear algebra helpers (blas.hip)
+// C[M x N] = alpha * op(A) op(B) (+ beta C); row-major; op(A) = A[M x K] or A^T
+// (A stored K x M); wK (may be NULL) weights the sum over k.
+efe_status efe_gemm(efe_ctx *ctx, bool transA, bool transB, int64_t M, int64_t N, int64_t K,
+                    double alpha, const double *A, int64_t lda, const double *B, int64_t ldb,
+                    double beta, double *C, int64_t ldc, const double *wK = nullptr);
+// C += alpha A^T diag(w) B over K rows split across blocks (C must be summed into)
+efe_status efe_gram(efe_ctx *ctx, int64_t M, int64_t N, int64_t K, double alpha,
+                    const double *A, int64_t lda, const double *B, int64_t ldb,
+                    const double *w, double *C, int64_t ldc);
+
+// operator applications (apply.hip)
+// Y = H^E X with X given as (XC scaled row-wise by `scale` if non-NULL, XE);
+// prec selects the cell GEMM / projector precision.
+efe_status efe_apply_H_internal(efe_ctx *ctx, const double *XC, int64_t ldx, const double *scale,
+                                const double *XE, int64_t lde, double *Y, int64_t ldy, int ncols,
+                                int prec);
+efe_status efe_apply_M_internal(efe_ctx *ctx, const double *X, int64_t ldx, double *Y,
+                                int64_t ldy, int ncols);
+efe_status efe_apply_Minv_internal(efe_ctx *ctx, const double *X, int64_t ldx, double *Y,
+                                   int64_t ldy, int ncols);
+efe_status efe_enr_block_inv(efe_ctx *ctx, const double *XE, int64_t ldx, double *YE,
+                             int64_t ldy, int ncols);
+
+// ------------------------------------------------------------------ timing
+// Optional HIP-event timing of the hot-path kernels (efe_timing).
+#define EFE_T_CELL 0     // one colour pass of the cell GEMM
+#define EFE_T_PRE 1      // pre pass of an H apply
+#define EFE_T_POST 2     // enrichment rows of an H apply
+#define EFE_T_RECUR 3    // residual recurrence update
+#define EFE_T_APPLY 4    // a whole H apply
+#define EFE_T_RR 5       // a whole Rayleigh-Ritz
+#define EFE_T_N 6
+int efe_timer_begin(efe_ctx *ctx, int which);
+void efe_timer_end(efe_ctx *ctx, int which, int slot);

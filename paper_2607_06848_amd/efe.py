@@ -1,0 +1,278 @@
+"""Thin ctypes binding of libefe.so (argument marshalling only).
+
+Every function below forwards to the C entry point of the same name declared
+in include/efe.h.  Device memory and streams come from PyTorch; all compute
+runs in the library's HIP kernels.  There is no fallback: if the library is
+not built or no GPU is present, the calls raise.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libefe.so")
+
+EFE_FP64, EFE_FP32, EFE_BF16 = 0, 1, 2
+EFE_FILTER_RESIDUAL, EFE_FILTER_STANDARD = 0, 1
+STATUS = {0: "EFE_OK", -1: "EFE_EINVAL", -2: "EFE_ENOMEM", -3: "EFE_EHIP",
+          -4: "EFE_ENOTCONV", -5: "EFE_ENUMERIC", -6: "EFE_ESTATE"}
+
+c_double_p = ctypes.POINTER(ctypes.c_double)
+c_int32_p = ctypes.POINTER(ctypes.c_int32)
+c_int64_p = ctypes.POINTER(ctypes.c_int64)
+c_uint8_p = ctypes.POINTER(ctypes.c_uint8)
+
+
+class MeshDesc(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
+                ("ncell", ctypes.c_int32 * 3), ("p", ctypes.c_int32), ("nq", ctypes.c_int32)]
+
+
+class SystemDesc(ctypes.Structure):
+    _fields_ = [("natoms", ctypes.c_int32), ("xyz", c_double_p), ("Z", c_double_p),
+                ("loc_rc", ctypes.c_double), ("loc_amp", ctypes.c_double),
+                ("loc_rg", ctypes.c_double), ("kb_width", ctypes.c_double),
+                ("kb_D", ctypes.c_double), ("kb_rcut", ctypes.c_double),
+                ("enr_lmax", ctypes.c_int32), ("enr_alpha", ctypes.c_double),
+                ("enr_rcut", ctypes.c_double), ("enr_t", ctypes.c_double),
+                ("rho_alpha", ctypes.c_double)]
+
+
+class ChebParams(ctypes.Structure):
+    _fields_ = [("degree", ctypes.c_int32), ("a", ctypes.c_double), ("b", ctypes.c_double),
+                ("a_min", ctypes.c_double), ("mode", ctypes.c_int32), ("prec", ctypes.c_int32)]
+
+
+class EFEError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+# name -> (restype, argtypes)
+_SIGS = {
+    "efe_setup_mesh": (ctypes.c_int32, [ctypes.POINTER(MeshDesc), ctypes.POINTER(SystemDesc),
+                                        ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "efe_get_sizes": (ctypes.c_int32, [ctypes.c_void_p, c_int64_p]),
+    "efe_get_tables": (ctypes.c_int32, [ctypes.c_void_p, c_int32_p, c_int32_p, c_int32_p,
+                                        c_uint8_p]),
+    "efe_get_support": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, c_int64_p, c_int32_p,
+                                         c_int32_p]),
+    "efe_local_potential": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p]),
+    "efe_set_potential": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]),
+    "efe_apply_H": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_int32, ctypes.c_int64]),
+    "efe_apply_M": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_int32, ctypes.c_int64]),
+    "efe_apply_Minv_approx": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                               ctypes.c_int32, ctypes.c_int64]),
+    "efe_spectrum_upper_bound": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p,
+                                                  ctypes.c_int32, c_double_p]),
+    "efe_cheb_filter": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_int32, ctypes.c_int64,
+                                         ctypes.POINTER(ChebParams)]),
+    "efe_rayleigh_ritz": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                           ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]),
+    "efe_timing": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
+    "efe_timing_get": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, c_int64_p, c_double_p]),
+    "efe_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
+    "efe_destroy": (None, [ctypes.c_void_p]),
+}
+
+
+def lib():
+    """Load libefe.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """A library context for one mesh and system (efe_setup_mesh)."""
+
+    def __init__(self, w, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("the EFE library needs a GPU")
+        L = lib()
+        self.w = w
+        md = MeshDesc()
+        md.lo[:] = [float(v) for v in w["lo"]]
+        md.hi[:] = [float(v) for v in w["hi"]]
+        md.ncell[:] = [int(v) for v in w["ncell"]]
+        md.p = int(w["p"])
+        md.nq = int(w["nq"])
+        self._xyz = np.ascontiguousarray(np.asarray(w["xyz"], np.float64).reshape(-1, 3))
+        self._Z = np.ascontiguousarray(np.asarray(w.get("Zs", np.full(len(self._xyz), w.get("Z", 0.0))),
+                                                  np.float64))
+        sd = SystemDesc()
+        sd.natoms = self._xyz.shape[0]
+        sd.xyz = self._xyz.ctypes.data_as(c_double_p)
+        sd.Z = self._Z.ctypes.data_as(c_double_p)
+        for k in ("loc_rc", "loc_amp", "loc_rg", "kb_width", "kb_D", "kb_rcut", "enr_alpha",
+                  "enr_rcut", "enr_t", "rho_alpha"):
+            setattr(sd, k, float(w.get(k, 0.0)))
+        sd.enr_lmax = int(w.get("enr_lmax", -1))
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self.stream = stream
+        h = ctypes.c_void_p()
+        st = L.efe_setup_mesh(ctypes.byref(md), ctypes.byref(sd), ctypes.c_void_p(stream),
+                              ctypes.byref(h))
+        if st != 0:
+            raise EFEError(st, L.efe_last_error(None).decode())
+        self.h = h
+        sz = (ctypes.c_int64 * 8)()
+        self._check(L.efe_get_sizes(self.h, sz))
+        (self.rows, self.n_nodes, self.n_dof, self.n_enr, self.n_cells, self.n_qpts,
+         self.natoms, self.nloc) = [int(v) for v in sz]
+
+    # -------------------------------------------------------------- util
+    def _check(self, st):
+        if st != 0:
+            raise EFEError(st, lib().efe_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().efe_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _block(X):
+        import torch
+        if not (X.is_cuda and X.dtype == torch.float64 and X.dim() == 2 and X.stride(1) == 1):
+            raise ValueError("blocks are 2-D float64 CUDA tensors with unit column stride")
+        return X.shape[1], X.stride(0)
+
+    def empty(self, ncols, ld=None):
+        """Zeroed block (rows x ncols) with leading dimension ld (default ncols)."""
+        import torch
+        ld = ncols if ld is None else ld
+        return torch.zeros((self.rows, ld), dtype=torch.float64, device="cuda")[:, :ncols]
+
+    # -------------------------------------------------------------- timing
+    TIMERS = {"cell": 0, "pre": 1, "post": 2, "recur": 3, "apply": 4, "rr": 5}
+
+    def timing(self, enable):
+        self._check(lib().efe_timing(self.h, 1 if enable else 0))
+
+    def timing_get(self, which):
+        n = ctypes.c_int64()
+        ms = ctypes.c_double()
+        self._check(lib().efe_timing_get(self.h, self.TIMERS[which], ctypes.byref(n),
+                                         ctypes.byref(ms)))
+        return n.value, ms.value
+
+    # -------------------------------------------------------------- tables
+    def tables(self):
+        c2g = np.empty(self.n_cells * self.nloc, np.int32)
+        order = np.empty(self.n_cells, np.int32)
+        offs = np.empty(9, np.int32)
+        bnd = np.empty(self.n_nodes, np.uint8)
+        self._check(lib().efe_get_tables(self.h, c2g.ctypes.data_as(c_int32_p),
+                                         order.ctypes.data_as(c_int32_p),
+                                         offs.ctypes.data_as(c_int32_p),
+                                         bnd.ctypes.data_as(c_uint8_p)))
+        return dict(cell_to_global=c2g.reshape(self.n_cells, self.nloc), colour_order=order,
+                    colour_offsets=offs, boundary=bnd)
+
+    def support(self, which):
+        n = ctypes.c_int64()
+        self._check(lib().efe_get_support(self.h, which, ctypes.byref(n), None, None))
+        ptr = np.empty(self.natoms + 1, np.int32)
+        cells = np.empty(max(n.value, 1), np.int32)
+        self._check(lib().efe_get_support(self.h, which, ctypes.byref(n),
+                                          ptr.ctypes.data_as(c_int32_p),
+                                          cells.ctypes.data_as(c_int32_p)))
+        return ptr, cells[:n.value]
+
+    # -------------------------------------------------------------- operators
+    def local_potential(self):
+        import torch
+        vq = torch.empty(self.n_qpts, dtype=torch.float64, device="cuda")
+        self._check(lib().efe_local_potential(self.h, _ptr(vq)))
+        return vq
+
+    def set_potential(self, vq, precisions=0):
+        self._check(lib().efe_set_potential(self.h, _ptr(vq), int(precisions)))
+
+    def apply_H(self, X, Y=None):
+        n, ld = self._block(X)
+        Y = self.empty(n, ld) if Y is None else Y
+        self._check(lib().efe_apply_H(self.h, _ptr(X), _ptr(Y), n, ld))
+        return Y
+
+    def apply_M(self, X, Y=None):
+        n, ld = self._block(X)
+        Y = self.empty(n, ld) if Y is None else Y
+        self._check(lib().efe_apply_M(self.h, _ptr(X), _ptr(Y), n, ld))
+        return Y
+
+    def apply_Minv_approx(self, X, Y=None):
+        n, ld = self._block(X)
+        Y = self.empty(n, ld) if Y is None else Y
+        self._check(lib().efe_apply_Minv_approx(self.h, _ptr(X), _ptr(Y), n, ld))
+        return Y
+
+    def spectrum_upper_bound(self, v0, steps=20):
+        b = ctypes.c_double()
+        self._check(lib().efe_spectrum_upper_bound(self.h, _ptr(v0), int(steps), ctypes.byref(b)))
+        return b.value
+
+    def cheb_filter(self, V, lam, degree, a, b, a_min, mode=EFE_FILTER_RESIDUAL, prec=EFE_FP64):
+        n, ld = self._block(V)
+        p = ChebParams(int(degree), float(a), float(b), float(a_min), int(mode), int(prec))
+        lp = _ptr(lam) if lam is not None else None
+        self._check(lib().efe_cheb_filter(self.h, _ptr(V), lp, n, ld, ctypes.byref(p)))
+        return V
+
+    def rayleigh_ritz(self, V, want_res=True):
+        import torch
+        n, ld = self._block(V)
+        lam = torch.empty(n, dtype=torch.float64, device="cuda")
+        res = torch.empty(n, dtype=torch.float64, device="cuda") if want_res else None
+        self._check(lib().efe_rayleigh_ritz(self.h, _ptr(V), n, ld, _ptr(lam),
+                                            _ptr(res) if res is not None else None))
+        return lam, res
+
+
+# module-level names of the C entry points
+def efe_setup_mesh(workload, stream=None):
+    return Context(workload, stream)
+
+
+def efe_apply_H(ctx, X, Y=None):
+    return ctx.apply_H(X, Y)
+
+
+def efe_cheb_filter(ctx, V, lam, degree, a, b, a_min, mode=EFE_FILTER_RESIDUAL, prec=EFE_FP64):
+    return ctx.cheb_filter(V, lam, degree, a, b, a_min, mode, prec)
+
+
+def efe_rayleigh_ritz(ctx, V):
+    return ctx.rayleigh_ritz(V)
