@@ -59,7 +59,7 @@ typedef struct efe_ctx efe_ctx;
 typedef struct {
   double lo[3], hi[3];
   int32_t ncell[3];
-  int32_t p;    /* 1 <= p <= 7 */
+  int32_t p;    /* 1 <= p <= 6 */
   int32_t nq;   /* 1 <= nq <= 7 */
 } efe_mesh_desc;
 
@@ -156,6 +156,47 @@ efe_status efe_cheb_filter(efe_ctx *ctx, double *V, const double *lambda, int32_
  * Returns EFE_ENUMERIC if S is not positive definite. */
 efe_status efe_rayleigh_ritz(efe_ctx *ctx, double *V, int32_t ncols, int64_t ld,
                              double *lambda, double *resnorm);
+
+/* ---------------------------------------------------------------- SCF
+ * Self-consistent field around the eigensolver (Sec. II.A, III.C): LDA
+ * (Perdew-Wang 1992), phi = phi^at + phi^rem with phi^rem from a CFE Poisson
+ * problem for rho - sum_I rho^(I) (homogeneous Dirichlet, Jacobi CG),
+ * Fermi-Dirac occupations, Anderson mixing of rho at the Gauss points. */
+typedef struct {
+  int32_t passes_first;  /* filter + Rayleigh-Ritz passes in the first step */
+  int32_t passes;        /* passes in later steps */
+  int32_t degree;        /* Chebyshev degree */
+  int32_t prec;          /* filter precision (EFE_FP64 / EFE_FP32 / EFE_BF16) */
+  double kT;             /* smearing temperature in Ha */
+  double mix_beta;       /* Anderson damping */
+  int32_t mix_history;   /* Anderson history depth, 0..16 */
+  double cg_rtol;        /* Poisson CG relative residual */
+  int32_t cg_maxit;
+  int32_t lanczos_steps; /* spectrum bound per step */
+} efe_scf_params;
+
+typedef struct {
+  double E, F, E_band, E_xc, E_el; /* energies at the output density (Ha)      */
+  double mu, n_el, drho, dE;       /* Fermi level, int rho_out, ||rho_out - rho_in||, E - E_prev */
+  double max_occ_res, b;           /* largest residual of occupied states, bound */
+  double t_poisson_ms, t_filter_ms, t_rr_ms, t_density_ms, t_other_ms;
+  int32_t iter, passes, cg_iters;
+} efe_scf_report;
+
+/* Input density of the next SCF step (device, n_qpts, Gauss points cell by
+ * cell); resets the mixing history.  Without a call the first step starts
+ * from the superposition of atomic densities. */
+efe_status efe_set_density(efe_ctx *ctx, const double *rho_q);
+/* Copy a density (device, n_qpts): which = 0 input of the next step, 1 output
+ * of the last step, 2 superposition of atomic densities. */
+efe_status efe_get_density(efe_ctx *ctx, int32_t which, double *out);
+/* One SCF step.  V (rows x ld, device) holds the N-vector subspace: any block
+ * before the first step (it is Rayleigh-Ritz orthonormalized first), the Ritz
+ * vectors after each step; lambda (device, N) their values; v0 (device, rows)
+ * the Lanczos start vector.  The report (host) carries the energies of the
+ * step.  Convergence is decided by the caller (e.g. |dE| / N_atoms < tol). */
+efe_status efe_scf_step(efe_ctx *ctx, double *V, int32_t ncols, int64_t ld, double *lambda,
+                        const double *v0, const efe_scf_params *prm, efe_scf_report *rep);
 
 /* Kernel timing.  enable != 0 clears earlier records and starts recording HIP
  * events on the context's stream around the tracked launches; 0 stops.

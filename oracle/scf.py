@@ -152,6 +152,8 @@ class Electrostatics:
         rz = r @ z
         bn = np.sqrt(b @ b)
         it = 0
+        if bn == 0.0:            # zero source: zero potential
+            return np.zeros_like(b), 0
         while np.sqrt(r @ r) > rtol * bn and it < maxit:
             Ap = self.K(p)
             alpha = rz / (p @ Ap)

@@ -24,7 +24,7 @@ __global__ __launch_bounds__(256) void k_pre(int64_t n_nodes, int ncols, const d
                                              const double *__restrict__ C_nm,
                                              const double *__restrict__ B_nm, int nf,
                                              double *__restrict__ Xh, int64_t ldh,
-                                             double *__restrict__ Y, int64_t ldy) {
+                                             double *Y, int64_t ldy) {
   const int64_t j = (int64_t)blockIdx.x * 4 + threadIdx.y;
   if (j >= n_nodes) return;
   const bool inner = minv[j] != 0.0;
@@ -41,12 +41,12 @@ __global__ __launch_bounds__(256) void k_pre(int64_t n_nodes, int ncols, const d
         for (int k = 0; k < nf; ++k) {
           const double v = xe[(int64_t)k * lde];
           xh -= cc[k] * v;
-          y += bb[k] * v;
+          if (Y) y += bb[k] * v;
         }
       }
     }
     Xh[j * ldh + col] = xh;
-    Y[j * ldy + col] = y;
+    if (Y) Y[j * ldy + col] = y;
   }
 }
 
@@ -310,6 +310,17 @@ efe_status efe_apply_H_internal(efe_ctx *c, const double *XC, int64_t ldx, const
   }
   efe_timer_end(c, EFE_T_POST, t_post);
   efe_timer_end(c, EFE_T_APPLY, t_apply);
+  HIPCHK(c, hipGetLastError());
+  return EFE_OK;
+}
+
+efe_status efe_transform_cfe(efe_ctx *c, const double *X, int64_t ldx, double *Xh, int64_t ldh,
+                             int ncols) {
+  if (ncols <= 0) return EFE_OK;
+  dim3 blk(64, 4);
+  k_pre<<<cdiv(c->n_nodes, 4), blk, 0, c->stream>>>(
+      c->n_nodes, ncols, X, ldx, nullptr, c->d_minv, X + c->n_nodes * ldx, ldx, c->d_nm_ptr,
+      c->d_nm_atom, c->d_C_nm, c->d_B_nm, c->nf, Xh, ldh, nullptr, 0);
   HIPCHK(c, hipGetLastError());
   return EFE_OK;
 }

@@ -12,8 +12,9 @@
 
 #include "../../include/efe.h"
 
-#define EFE_MAXP 7
+#define EFE_MAXP 6
 #define EFE_MAXQ 7
+#define EFE_MAXLOC ((EFE_MAXP + 1) * (EFE_MAXP + 1) * (EFE_MAXP + 1))
 
 struct DevBuf {
   void *p = nullptr;
@@ -95,6 +96,9 @@ struct efe_ctx {
   // workspaces (grown on demand)
   std::vector<DevBuf> ws;
 
+  // SCF state (scf.hip)
+  void *scf = nullptr;
+
   // event timing (efe_timing)
   bool timing = false;
   std::vector<hipEvent_t> tev[6];   // start/stop pairs per kernel class
@@ -151,6 +155,10 @@ efe_status efe_apply_M_internal(efe_ctx *ctx, const double *X, int64_t ldx, doub
                                 int64_t ldy, int ncols);
 efe_status efe_apply_Minv_internal(efe_ctx *ctx, const double *X, int64_t ldx, double *Y,
                                    int64_t ldy, int ncols);
+// Xh = X^C - C^T X^E on interior CFE rows (0 on the boundary)
+efe_status efe_transform_cfe(efe_ctx *ctx, const double *X, int64_t ldx, double *Xh, int64_t ldh,
+                             int ncols);
+void efe_scf_free(efe_ctx *ctx);
 efe_status efe_enr_block_inv(efe_ctx *ctx, const double *XE, int64_t ldx, double *YE,
                              int64_t ldy, int ncols);
 

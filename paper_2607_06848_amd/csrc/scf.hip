@@ -1,0 +1,783 @@
+// Self-consistent field support (Sec. II.A, III.C; Fermi-Dirac smearing and
+// Anderson mixing of Sec. IV):
+//   rho_in -> Poisson for phi^rem (CFE stiffness, Jacobi CG) -> v_eff =
+//   phi^at + phi^rem + v_short + v_xc(rho_in) -> operators -> Lanczos bound
+//   -> residual-filter passes + Rayleigh-Ritz -> Fermi level -> rho_out ->
+//   energies at rho_out -> Anderson update of rho_in.
+// Energies at the output density:
+//   E = 2 sum f eps - int rho_out v_in + E_xc[rho_out] + E_el[rho_out],
+//   E_el = 1/2 sum_IJ <n_I, n_J> - E_self + dE_ZZ + int Drho phi^at
+//          + 1/2 int Drho phi^rem[rho_out] + int rho_out v_short,
+//   F = E - T S.  LDA is Perdew-Wang 1992 (unpolarized), zero for rho <= 1e-14.
+#include <chrono>
+#include <cmath>
+#include <vector>
+
+#include "efe_device.h"
+
+#define KB_HA_PER_K 3.166811563e-6
+
+// ------------------------------------------------------------------ state
+struct ScfState {
+  bool init = false;
+  double *rho_at = nullptr, *phi_at = nullptr, *v_short = nullptr;   // [n_qpts]
+  double *rho_in = nullptr, *rho_out = nullptr, *v_in = nullptr, *phiq = nullptr;
+  double *phi_rem = nullptr, *phi_out = nullptr;                      // [n_nodes]
+  double *Kdiag = nullptr;                                            // [n_nodes]
+  double *cg = nullptr;                                               // r, z, p, Ap, b
+  double *hist = nullptr;                                             // Anderson X, F ring
+  double *scal = nullptr;                                             // device scalars
+  double *f = nullptr;                                                // occupations [N]
+  int32_t *cell_ptr = nullptr, *cell_atom = nullptr;                  // cell -> atoms
+  double e_const = 0.0;
+  int iter = 0, nhist = 0, hist_m = 0;
+  double E_prev = 0.0;
+  bool have_E = false;
+};
+
+static ScfState &S(efe_ctx *c) {
+  static_assert(sizeof(void *) == 8, "64-bit only");
+  if (!c->scf) c->scf = new ScfState();
+  return *(ScfState *)c->scf;
+}
+
+void efe_scf_free(efe_ctx *c) {
+  if (!c->scf) return;
+  ScfState &s = *(ScfState *)c->scf;
+  void *ptrs[] = {s.rho_at, s.phi_at, s.v_short, s.rho_in, s.rho_out, s.v_in, s.phiq,
+                  s.phi_rem, s.phi_out, s.Kdiag, s.cg, s.hist, s.scal, s.f, s.cell_ptr,
+                  s.cell_atom};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  delete (ScfState *)c->scf;
+  c->scf = nullptr;
+}
+
+// ------------------------------------------------------------------ kernels
+__device__ inline double erf_over_r(double r, double a) {
+  const double x = r / a;
+  return x < 1e-6 ? (2.0 / (a * sqrt(M_PI))) * (1.0 - x * x / 3.0) : erf(x) / r;
+}
+
+// rho^(I), phi^(I) and v_short summed over atoms at every Gauss point
+__global__ void k_atomic_fields(MeshGeo g, const double *__restrict__ xq1, int natoms,
+                                const double *__restrict__ xyz, const double *__restrict__ Z,
+                                double a_rho, double rb, double amp, double rg,
+                                double *__restrict__ rho_at, double *__restrict__ phi_at,
+                                double *__restrict__ v_short) {
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t nq = (int64_t)g.ncell[0] * g.ncell[1] * g.ncell[2] * g.nqp;
+  if (idx >= nq) return;
+  double x[3];
+  quad_point(g, xq1, (int)(idx / g.nqp), (int)(idx % g.nqp), x);
+  double ra = 0.0, pa = 0.0, vs = 0.0;
+  const double norm = pow(a_rho / M_PI, 1.5);
+  for (int I = 0; I < natoms; ++I) {
+    const double dx = x[0] - xyz[3 * I], dy = x[1] - xyz[3 * I + 1], dz = x[2] - xyz[3 * I + 2];
+    const double r2 = dx * dx + dy * dy + dz * dz, r = sqrt(r2);
+    ra += Z[I] * norm * exp(-a_rho * r2);
+    pa += Z[I] * (erf_over_r(r, 1.0 / sqrt(a_rho)) - erf_over_r(r, rb));
+    vs += amp * exp(-(r / rg) * (r / rg));
+  }
+  rho_at[idx] = ra;
+  phi_at[idx] = pa;
+  v_short[idx] = vs;
+}
+
+// <g_a, g_b>(R) for unit Gaussians with exponents a, b
+__device__ inline double gauss_coulomb(double R, double a, double b) {
+  const double mu = sqrt(a * b / (a + b));
+  return erf_over_r(R, 1.0 / mu);
+}
+
+// 1/2 sum_IJ <n_I, n_J> - E_self + dE_ZZ (one thread per ordered pair)
+__global__ void k_const_energy(int natoms, const double *__restrict__ xyz,
+                               const double *__restrict__ Z, double a_rho, double rb,
+                               double *__restrict__ out) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (int64_t)natoms * natoms) return;
+  const int i = t / natoms, j = t % natoms;
+  const double dx = xyz[3 * i] - xyz[3 * j], dy = xyz[3 * i + 1] - xyz[3 * j + 1],
+               dz = xyz[3 * i + 2] - xyz[3 * j + 2];
+  const double R = sqrt(dx * dx + dy * dy + dz * dz);
+  const double ab = 1.0 / (rb * rb);
+  double e = 0.5 * Z[i] * Z[j] *
+             (gauss_coulomb(R, a_rho, a_rho) - 2.0 * gauss_coulomb(R, a_rho, ab) +
+              gauss_coulomb(R, ab, ab));
+  if (i == j) e -= Z[i] * Z[i] / (sqrt(2.0 * M_PI) * rb);
+  if (i < j) e += Z[i] * Z[j] * erfc(R / (sqrt(2.0) * rb)) / R;
+  atomicAdd(out, e);
+}
+
+// diagonal of the assembled stiffness (1 on boundary nodes)
+__global__ void k_kdiag(int64_t n_cells, int nloc, const int32_t *__restrict__ c2g,
+                        const double *__restrict__ K, double *__restrict__ d) {
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= n_cells * nloc) return;
+  const int l = idx % nloc;
+  atomicAdd(&d[c2g[idx]], K[(int64_t)l * nloc + l]);
+}
+
+__global__ void k_kdiag_fix(int64_t n, const double *__restrict__ minv, double *__restrict__ d) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n && minv[i] == 0.0) d[i] = 1.0;
+}
+
+// f_j += 4 pi sum_q W fq N_l on interior nodes (one block per cell)
+__global__ __launch_bounds__(256) void k_load_vector(int nloc, int nqp, const int32_t *__restrict__ c2g,
+                                                     const double *__restrict__ N3,
+                                                     const double *__restrict__ W3,
+                                                     const double *__restrict__ fq,
+                                                     const double *__restrict__ sub,
+                                                     const double *__restrict__ minv,
+                                                     double scale, double *__restrict__ out) {
+  __shared__ double wf[EFE_MAXQ * EFE_MAXQ * EFE_MAXQ];
+  const int64_t cell = blockIdx.x;
+  for (int q = threadIdx.x; q < nqp; q += blockDim.x)
+    wf[q] = W3[q] * (fq[cell * nqp + q] - (sub ? sub[cell * nqp + q] : 0.0));
+  __syncthreads();
+  for (int l = threadIdx.x; l < nloc; l += blockDim.x) {
+    const int32_t node = c2g[cell * nloc + l];
+    if (minv[node] == 0.0) continue;
+    double acc = 0.0;
+    for (int q = 0; q < nqp; ++q) acc += wf[q] * N3[(int64_t)q * nloc + l];
+    atomicAdd(&out[node], scale * acc);
+  }
+}
+
+// y += K x on interior nodes for the cells of one colour (shared cell matrix)
+__global__ __launch_bounds__(256) void k_stiff_apply(int ncells, const int32_t *__restrict__ cells,
+                                                     int nloc, const int32_t *__restrict__ c2g,
+                                                     const double *__restrict__ K,
+                                                     const double *__restrict__ x,
+                                                     const double *__restrict__ minv,
+                                                     double *__restrict__ y) {
+  __shared__ double xs[EFE_MAXLOC];
+  const int ci = blockIdx.x;
+  if (ci >= ncells) return;
+  const int64_t cell = cells[ci];
+  for (int l = threadIdx.x; l < nloc; l += blockDim.x) {
+    const int32_t node = c2g[cell * nloc + l];
+    xs[l] = minv[node] == 0.0 ? 0.0 : x[node];
+  }
+  __syncthreads();
+  for (int l = threadIdx.x; l < nloc; l += blockDim.x) {
+    const int32_t node = c2g[cell * nloc + l];
+    if (minv[node] == 0.0) continue;
+    const double *kr = K + (int64_t)l * nloc;
+    double acc = 0.0;
+    for (int m = 0; m < nloc; ++m) acc += kr[m] * xs[m];
+    y[node] += acc;
+  }
+}
+
+// nodal field -> Gauss points (one block per cell)
+__global__ __launch_bounds__(256) void k_nodes_to_quad(int nloc, int nqp, const int32_t *__restrict__ c2g,
+                                                       const double *__restrict__ N3,
+                                                       const double *__restrict__ x,
+                                                       const double *__restrict__ minv,
+                                                       double *__restrict__ xq) {
+  __shared__ double xs[EFE_MAXLOC];
+  const int64_t cell = blockIdx.x;
+  for (int l = threadIdx.x; l < nloc; l += blockDim.x) {
+    const int32_t node = c2g[cell * nloc + l];
+    xs[l] = minv[node] == 0.0 ? 0.0 : x[node];
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < nqp; q += blockDim.x) {
+    const double *nr = N3 + (int64_t)q * nloc;
+    double acc = 0.0;
+    for (int l = 0; l < nloc; ++l) acc += nr[l] * xs[l];
+    xq[cell * nqp + q] = acc;
+  }
+}
+
+// PW92 LDA (unpolarized): energy per electron and potential
+__device__ inline void lda_pw92(double rho, double &exc, double &vxc) {
+  if (!(rho > 1e-14)) {
+    exc = 0.0;
+    vxc = 0.0;
+    return;
+  }
+  const double ex = -0.75 * cbrt(3.0 / M_PI) * cbrt(rho);
+  const double vx = 4.0 / 3.0 * ex;
+  const double rs = cbrt(3.0 / (4.0 * M_PI * rho));
+  const double A = 0.031091, a1 = 0.21370, b1 = 7.5957, b2 = 3.5876, b3 = 1.6382, b4 = 0.49294;
+  const double srs = sqrt(rs);
+  const double Q0 = -2.0 * A * (1.0 + a1 * rs);
+  const double Q1 = 2.0 * A * (b1 * srs + b2 * rs + b3 * rs * srs + b4 * rs * rs);
+  const double Q1p = A * (b1 / srs + 2.0 * b2 + 3.0 * b3 * srs + 4.0 * b4 * rs);
+  const double L = log1p(1.0 / Q1);
+  const double ec = Q0 * L;
+  const double dec = -2.0 * A * a1 * L - Q0 * Q1p / (Q1 * Q1 + Q1);
+  exc = ex + ec;
+  vxc = vx + ec - rs / 3.0 * dec;
+}
+
+// v_in = phi_at + phi_rem(q) + v_short + v_xc(rho_in)
+__global__ void k_veff(int64_t n, const double *__restrict__ rho, const double *__restrict__ phi_at,
+                       const double *__restrict__ phiq, const double *__restrict__ vs,
+                       double *__restrict__ v) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double exc, vxc;
+  lda_pw92(rho[i], exc, vxc);
+  v[i] = phi_at[i] + phiq[i] + vs[i] + vxc;
+}
+
+// Fermi level by bisection (one thread): 2 sum f = Ne; writes mu, f, band, TS
+__global__ void k_fermi(int N, const double *__restrict__ lam, double ne, double kT,
+                        double *__restrict__ f, double *__restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double lo = lam[0], hi = lam[0];
+  for (int i = 1; i < N; ++i) {
+    lo = fmin(lo, lam[i]);
+    hi = fmax(hi, lam[i]);
+  }
+  lo -= 50.0 * kT + 1.0;
+  hi += 50.0 * kT + 1.0;
+  for (int it = 0; it < 200; ++it) {
+    const double mu = 0.5 * (lo + hi);
+    double s = 0.0;
+    for (int i = 0; i < N; ++i) s += 1.0 / (1.0 + exp((lam[i] - mu) / kT));
+    if (2.0 * s < ne) lo = mu;
+    else hi = mu;
+  }
+  const double mu = 0.5 * (lo + hi);
+  double band = 0.0, ts = 0.0;
+  for (int i = 0; i < N; ++i) {
+    const double x = (lam[i] - mu) / kT;
+    const double fi = x > 0 ? exp(-x) / (1.0 + exp(-x)) : 1.0 / (1.0 + exp(x));
+    f[i] = fi;
+    band += 2.0 * fi * lam[i];
+    if (fi > 0.0 && fi < 1.0) ts += fi * log(fi) + (1.0 - fi) * log(1.0 - fi);
+  }
+  out[0] = mu;
+  out[1] = band;
+  out[2] = -2.0 * kT * ts;
+}
+
+// rho(q) = 2 sum_j f_j psi_j(q)^2, psi = N3 Xh_cell + sum_I phi_I(q) V^E_I
+// (one block per cell; columns in chunks of 16, only the listed columns)
+__global__ __launch_bounds__(256) void k_density(MeshGeo g, EnrParam e, const double *__restrict__ xq1,
+                                                 const int32_t *__restrict__ c2g,
+                                                 const double *__restrict__ N3,
+                                                 const double *__restrict__ Xh, int64_t ldh,
+                                                 const double *__restrict__ VE, int64_t lde,
+                                                 const int32_t *__restrict__ cols, int ncols_occ,
+                                                 const double *__restrict__ f,
+                                                 const int32_t *__restrict__ cell_ptr,
+                                                 const int32_t *__restrict__ cell_atom,
+                                                 const double *__restrict__ xyz,
+                                                 const double *__restrict__ nu,
+                                                 double *__restrict__ rho) {
+  __shared__ double xs[EFE_MAXLOC][16];
+  __shared__ double ve[16][16 * 9];      // up to 16 atoms of the cell at a time
+  const int64_t cell = blockIdx.x;
+  const int nloc = g.nloc, nqp = g.nqp, nf = e.nf;
+  const int a0 = cell_ptr[cell], a1 = cell_ptr[cell + 1];
+  double racc[2] = {0.0, 0.0};
+  for (int c0 = 0; c0 < ncols_occ; c0 += 16) {
+    const int nc = min(16, ncols_occ - c0);
+    for (int idx = threadIdx.x; idx < nloc * 16; idx += blockDim.x) {
+      const int l = idx / 16, j = idx % 16;
+      xs[l][j] = j < nc ? Xh[(int64_t)c2g[cell * nloc + l] * ldh + cols[c0 + j]] : 0.0;
+    }
+    __syncthreads();
+    for (int r = 0; r < 2; ++r) {
+      const int q = threadIdx.x + 256 * r;
+      double psi[16];
+      for (int j = 0; j < 16; ++j) psi[j] = 0.0;
+      if (q < nqp) {
+        const double *nr = N3 + (int64_t)q * nloc;
+        for (int l = 0; l < nloc; ++l) {
+          const double n = nr[l];
+          for (int j = 0; j < 16; ++j) psi[j] += n * xs[l][j];
+        }
+      }
+      // enrichment part, atoms of this cell in groups of 16
+      for (int ab = a0; ab < a1; ab += 16) {
+        const int na = min(16, a1 - ab);
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < na * nf * 16; idx += blockDim.x) {
+          const int ia = idx / (nf * 16), k = (idx / 16) % nf, j = idx % 16;
+          const int I = cell_atom[ab + ia];
+          ve[j][ia * nf + k] =
+              j < nc ? nu[I * nf + k] * VE[(int64_t)(I * nf + k) * lde + cols[c0 + j]] : 0.0;
+        }
+        __syncthreads();
+        if (q < nqp) {
+          double x[3], phi[9];
+          quad_point(g, xq1, (int)cell, q, x);
+          for (int ia = 0; ia < na; ++ia) {
+            const int I = cell_atom[ab + ia];
+            enr_eval(e, x[0] - xyz[3 * I], x[1] - xyz[3 * I + 1], x[2] - xyz[3 * I + 2], phi,
+                     nullptr);
+            for (int k = 0; k < nf; ++k)
+              for (int j = 0; j < 16; ++j) psi[j] += phi[k] * ve[j][ia * nf + k];
+          }
+        }
+      }
+      if (q < nqp)
+        for (int j = 0; j < nc; ++j) racc[r] += 2.0 * f[cols[c0 + j]] * psi[j] * psi[j];
+    }
+    __syncthreads();
+  }
+  for (int r = 0; r < 2; ++r) {
+    const int q = threadIdx.x + 256 * r;
+    if (q < nqp) rho[cell * nqp + q] = racc[r];
+  }
+}
+
+// energy integrals over the Gauss points:
+// out[0] int rho v_in, [1] int rho eps_xc, [2] int Drho phi_at, [3] int Drho phiq,
+// [4] int rho v_short, [5] int rho, [6] int (rho - rho_in)^2
+__global__ void k_energy_sums(int64_t nq_tot, int nqp, const double *__restrict__ W3,
+                              const double *__restrict__ rho, const double *__restrict__ v_in,
+                              const double *__restrict__ rho_at, const double *__restrict__ phi_at,
+                              const double *__restrict__ phiq, const double *__restrict__ vs,
+                              const double *__restrict__ rho_in, double *__restrict__ out) {
+  __shared__ double red[7][256];
+  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nq_tot;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double w = W3[i % nqp], r = rho[i], dr = r - rho_at[i];
+    double exc, vxc;
+    lda_pw92(r, exc, vxc);
+    const double d = r - rho_in[i];
+    acc[0] += w * r * v_in[i];
+    acc[1] += w * r * exc;
+    acc[2] += w * dr * phi_at[i];
+    acc[3] += w * dr * phiq[i];
+    acc[4] += w * r * vs[i];
+    acc[5] += w * r;
+    acc[6] += w * d * d;
+  }
+  for (int k = 0; k < 7; ++k) red[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s)
+      for (int k = 0; k < 7; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x < 7) atomicAdd(&out[threadIdx.x], red[threadIdx.x][0]);
+}
+
+// weighted dot of two vectors over the Gauss points: out += sum W a b
+__global__ void k_wdot(int64_t n, int nqp, const double *__restrict__ W3,
+                       const double *__restrict__ a, const double *__restrict__ b,
+                       double *__restrict__ out) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    acc += (W3 ? W3[i % nqp] : 1.0) * a[i] * b[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(out, red[0]);
+}
+
+// y = a x + b y (vectors)
+__global__ void k_axpby(int64_t n, double a, const double *__restrict__ x, double b,
+                        double *__restrict__ y) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) y[i] = a * x[i] + b * y[i];
+}
+
+// z = r / d
+__global__ void k_precond(int64_t n, const double *__restrict__ r, const double *__restrict__ d,
+                          const double *__restrict__ minv, double *__restrict__ z) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) z[i] = minv[i] == 0.0 ? 0.0 : r[i] / d[i];
+}
+
+__global__ void k_sub(int64_t n, const double *__restrict__ a, const double *__restrict__ b,
+                      double *__restrict__ c) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) c[i] = a[i] - b[i];
+}
+
+// small dense solve A g = r (k x k, partial pivoting, one thread)
+__global__ void k_small_solve(int k, double *__restrict__ A, double *__restrict__ r,
+                              double *__restrict__ g) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int c = 0; c < k; ++c) {
+    int piv = c;
+    for (int i = c + 1; i < k; ++i)
+      if (fabs(A[i * k + c]) > fabs(A[piv * k + c])) piv = i;
+    if (piv != c) {
+      for (int j = 0; j < k; ++j) {
+        double t = A[c * k + j];
+        A[c * k + j] = A[piv * k + j];
+        A[piv * k + j] = t;
+      }
+      double t = r[c];
+      r[c] = r[piv];
+      r[piv] = t;
+    }
+    const double d = A[c * k + c];
+    for (int i = c + 1; i < k; ++i) {
+      const double fct = d != 0.0 ? A[i * k + c] / d : 0.0;
+      for (int j = c; j < k; ++j) A[i * k + j] -= fct * A[c * k + j];
+      r[i] -= fct * r[c];
+    }
+  }
+  for (int i = k - 1; i >= 0; --i) {
+    double s = r[i];
+    for (int j = i + 1; j < k; ++j) s -= A[i * k + j] * g[j];
+    g[i] = A[i * k + i] != 0.0 ? s / A[i * k + i] : 0.0;
+  }
+}
+
+// Anderson update: x = X_k - sum g_i (X_{i+1} - X_i) + beta (F_k - sum g_i (F_{i+1} - F_i))
+__global__ void k_anderson_update(int64_t n, int k, const double *__restrict__ X,
+                                  const double *__restrict__ F, int64_t stride,
+                                  const double *__restrict__ g, double beta,
+                                  double *__restrict__ out) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double x = X[(int64_t)k * stride + i], fk = F[(int64_t)k * stride + i];
+  for (int j = 0; j < k; ++j) {
+    const double dx = X[(int64_t)(j + 1) * stride + i] - X[(int64_t)j * stride + i];
+    const double df = F[(int64_t)(j + 1) * stride + i] - F[(int64_t)j * stride + i];
+    x -= g[j] * dx;
+    fk -= g[j] * df;
+  }
+  out[i] = x + beta * fk;
+}
+
+// ------------------------------------------------------------------ host
+static efe_status scf_init(efe_ctx *c) {
+  ScfState &s = S(c);
+  if (s.init) return EFE_OK;
+  efe_status st;
+  const int64_t nq = c->n_qpts, nn = c->n_nodes;
+  double **qs[] = {&s.rho_at, &s.phi_at, &s.v_short, &s.rho_in, &s.rho_out, &s.v_in, &s.phiq};
+  for (auto pp : qs)
+    if ((st = efe_alloc(c, (void **)pp, nq * 8))) return st;
+  double **ns[] = {&s.phi_rem, &s.phi_out, &s.Kdiag};
+  for (auto pp : ns)
+    if ((st = efe_alloc(c, (void **)pp, nn * 8))) return st;
+  if ((st = efe_alloc(c, (void **)&s.cg, 5 * nn * 8))) return st;
+  if ((st = efe_alloc(c, (void **)&s.scal, 256 * 8))) return st;
+  HIPCHK(c, hipMemsetAsync(s.phi_rem, 0, nn * 8, c->stream));
+  HIPCHK(c, hipMemsetAsync(s.Kdiag, 0, nn * 8, c->stream));
+  HIPCHK(c, hipMemsetAsync(s.scal, 0, 256 * 8, c->stream));
+  const MeshGeo g = mesh_geo(c);
+  k_atomic_fields<<<cdiv(nq, 256), 256, 0, c->stream>>>(g, c->d_xq1, c->natoms, c->d_xyz, c->d_Zs,
+                                                        c->rho_alpha, c->loc_rc, c->loc_amp,
+                                                        c->loc_rg, s.rho_at, s.phi_at, s.v_short);
+  if (c->natoms)
+    k_const_energy<<<cdiv((int64_t)c->natoms * c->natoms, 256), 256, 0, c->stream>>>(
+        c->natoms, c->d_xyz, c->d_Zs, c->rho_alpha, c->loc_rc, s.scal);
+  k_kdiag<<<cdiv(c->n_cells * c->nloc, 256), 256, 0, c->stream>>>(c->n_cells, c->nloc, c->d_c2g,
+                                                                   c->d_K, s.Kdiag);
+  k_kdiag_fix<<<cdiv(nn, 256), 256, 0, c->stream>>>(nn, c->d_minv, s.Kdiag);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipMemcpyAsync(&s.e_const, s.scal, 8, hipMemcpyDeviceToHost, c->stream));
+  // cell -> atoms whose enrichment support holds the cell
+  std::vector<int32_t> ptr(c->n_cells + 1, 0), lst;
+  {
+    std::vector<std::vector<int32_t>> per(c->n_cells);
+    for (int I = 0; I < c->natoms; ++I)
+      for (int32_t q = c->enr_ptr[I]; q < c->enr_ptr[I + 1]; ++q) per[c->enr_cells[q]].push_back(I);
+    for (int64_t cc = 0; cc < c->n_cells; ++cc) {
+      ptr[cc + 1] = ptr[cc] + (int32_t)per[cc].size();
+      lst.insert(lst.end(), per[cc].begin(), per[cc].end());
+    }
+  }
+  if ((st = efe_alloc(c, (void **)&s.cell_ptr, ptr.size() * 4))) return st;
+  if ((st = efe_alloc(c, (void **)&s.cell_atom, std::max<size_t>(lst.size(), 1) * 4))) return st;
+  HIPCHK(c, hipMemcpyAsync(s.cell_ptr, ptr.data(), ptr.size() * 4, hipMemcpyHostToDevice, c->stream));
+  if (!lst.empty())
+    HIPCHK(c, hipMemcpyAsync(s.cell_atom, lst.data(), lst.size() * 4, hipMemcpyHostToDevice,
+                             c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  // initial density: superposition of atomic densities
+  HIPCHK(c, hipMemcpyAsync(s.rho_in, s.rho_at, nq * 8, hipMemcpyDeviceToDevice, c->stream));
+  s.init = true;
+  return EFE_OK;
+}
+
+static efe_status stiff_apply(efe_ctx *c, const double *x, double *y) {
+  HIPCHK(c, hipMemsetAsync(y, 0, c->n_nodes * 8, c->stream));
+  for (int col = 0; col < 8; ++col) {
+    const int nc = c->colour_offsets[col + 1] - c->colour_offsets[col];
+    if (!nc) continue;
+    k_stiff_apply<<<nc, 256, 0, c->stream>>>(nc, c->d_colour_order + c->colour_offsets[col],
+                                             c->nloc, c->d_c2g, c->d_K, x, c->d_minv, y);
+  }
+  HIPCHK(c, hipGetLastError());
+  return EFE_OK;
+}
+
+static efe_status dot_host(efe_ctx *c, int64_t n, const double *a, const double *b, double *res) {
+  ScfState &s = S(c);
+  double *slot = s.scal + 64;
+  HIPCHK(c, hipMemsetAsync(slot, 0, 8, c->stream));
+  k_wdot<<<(unsigned)std::min<int64_t>(cdiv(n, 256), 1024), 256, 0, c->stream>>>(n, 1, nullptr, a,
+                                                                                b, slot);
+  HIPCHK(c, hipMemcpyAsync(res, slot, 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return EFE_OK;
+}
+
+// phi (in/out, nodes): K phi = 4 pi int (fq - sub) N, Jacobi-preconditioned CG
+static efe_status poisson(efe_ctx *c, const double *fq, const double *sub, double *phi, double rtol,
+                          int maxit, int *iters) {
+  ScfState &s = S(c);
+  const int64_t nn = c->n_nodes;
+  double *r = s.cg, *z = s.cg + nn, *p = s.cg + 2 * nn, *Ap = s.cg + 3 * nn, *b = s.cg + 4 * nn;
+  efe_status st;
+  const int T = 256;
+  HIPCHK(c, hipMemsetAsync(b, 0, nn * 8, c->stream));
+  k_load_vector<<<c->n_cells, 256, 0, c->stream>>>(c->nloc, c->nqp, c->d_c2g, c->d_N3, c->d_W3, fq,
+                                                   sub, c->d_minv, 4.0 * M_PI, b);
+  if ((st = stiff_apply(c, phi, Ap))) return st;
+  k_sub<<<cdiv(nn, T), T, 0, c->stream>>>(nn, b, Ap, r);
+  k_precond<<<cdiv(nn, T), T, 0, c->stream>>>(nn, r, s.Kdiag, c->d_minv, z);
+  HIPCHK(c, hipMemcpyAsync(p, z, nn * 8, hipMemcpyDeviceToDevice, c->stream));
+  double rz, bb, rr, pAp;
+  if ((st = dot_host(c, nn, r, z, &rz))) return st;
+  if ((st = dot_host(c, nn, b, b, &bb))) return st;
+  if ((st = dot_host(c, nn, r, r, &rr))) return st;
+  const double bn = sqrt(bb);
+  int it = 0;
+  if (bn == 0.0) {   // zero source: zero potential
+    HIPCHK(c, hipMemsetAsync(phi, 0, nn * 8, c->stream));
+    *iters = 0;
+    return EFE_OK;
+  }
+  while (sqrt(rr) > rtol * bn && it < maxit) {
+    if ((st = stiff_apply(c, p, Ap))) return st;
+    if ((st = dot_host(c, nn, p, Ap, &pAp))) return st;
+    const double alpha = rz / pAp;
+    k_axpby<<<cdiv(nn, T), T, 0, c->stream>>>(nn, alpha, p, 1.0, phi);
+    k_axpby<<<cdiv(nn, T), T, 0, c->stream>>>(nn, -alpha, Ap, 1.0, r);
+    if ((st = dot_host(c, nn, r, r, &rr))) return st;
+    k_precond<<<cdiv(nn, T), T, 0, c->stream>>>(nn, r, s.Kdiag, c->d_minv, z);
+    double rz_new;
+    if ((st = dot_host(c, nn, r, z, &rz_new))) return st;
+    k_axpby<<<cdiv(nn, T), T, 0, c->stream>>>(nn, 1.0, z, rz_new / rz, p);
+    rz = rz_new;
+    ++it;
+  }
+  HIPCHK(c, hipGetLastError());
+  *iters = it;
+  if (it >= maxit) EFE_FAIL(c, EFE_ENOTCONV, "Poisson CG did not converge");
+  return EFE_OK;
+}
+
+static double ms_since(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+extern "C" efe_status efe_set_density(efe_ctx *c, const double *rho) {
+  if (!c) return EFE_EINVAL;
+  if (!rho) EFE_FAIL(c, EFE_EINVAL, "null density");
+  efe_status st;
+  if ((st = scf_init(c))) return st;
+  ScfState &s = S(c);
+  HIPCHK(c, hipMemcpyAsync(s.rho_in, rho, c->n_qpts * 8, hipMemcpyDeviceToDevice, c->stream));
+  s.nhist = 0;
+  s.have_E = false;
+  s.iter = 0;
+  return EFE_OK;
+}
+
+extern "C" efe_status efe_get_density(efe_ctx *c, int32_t which, double *out) {
+  if (!c) return EFE_EINVAL;
+  if (!out || which < 0 || which > 2) EFE_FAIL(c, EFE_EINVAL, "bad arguments");
+  efe_status st;
+  if ((st = scf_init(c))) return st;
+  ScfState &s = S(c);
+  const double *src = which == 0 ? s.rho_in : which == 1 ? s.rho_out : s.rho_at;
+  HIPCHK(c, hipMemcpyAsync(out, src, c->n_qpts * 8, hipMemcpyDeviceToDevice, c->stream));
+  return EFE_OK;
+}
+
+extern "C" efe_status efe_scf_step(efe_ctx *c, double *V, int32_t N, int64_t ld, double *lambda,
+                                   const double *v0, const efe_scf_params *prm,
+                                   efe_scf_report *rep) {
+  if (!c) return EFE_EINVAL;
+  if (!V || !lambda || !v0 || !prm || !rep || N < 1 || ld < N)
+    EFE_FAIL(c, EFE_EINVAL, "bad arguments");
+  if (prm->degree < 1 || prm->passes < 1 || prm->passes_first < 1 || !(prm->kT > 0) ||
+      prm->mix_history < 0 || prm->mix_history > 16 || !(prm->cg_rtol > 0) || prm->cg_maxit < 1 ||
+      prm->lanczos_steps < 1)
+    EFE_FAIL(c, EFE_EINVAL, "bad SCF parameters");
+  efe_status st;
+  if ((st = scf_init(c))) return st;
+  ScfState &s = S(c);
+  const int64_t nq = c->n_qpts;
+  const int T = 256;
+  auto t0 = std::chrono::steady_clock::now();
+  double ne = 0.0;
+  for (double z : c->Z) ne += z;
+  // 1. potential of rho_in
+  int cg_it = 0, cg_it2 = 0;
+  if ((st = poisson(c, s.rho_in, s.rho_at, s.phi_rem, prm->cg_rtol, prm->cg_maxit, &cg_it)))
+    return st;
+  k_nodes_to_quad<<<c->n_cells, 256, 0, c->stream>>>(c->nloc, c->nqp, c->d_c2g, c->d_N3, s.phi_rem,
+                                                     c->d_minv, s.phiq);
+  k_veff<<<cdiv(nq, T), T, 0, c->stream>>>(nq, s.rho_in, s.phi_at, s.phiq, s.v_short, s.v_in);
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const double t_pois = ms_since(t0);
+  if ((st = efe_build_operators(c, s.v_in, prm->prec == EFE_FP64 ? 0 : (1 << prm->prec)))) return st;
+  // 2. eigen-solve passes
+  double b;
+  if ((st = efe_spectrum_upper_bound(c, v0, prm->lanczos_steps, &b))) return st;
+  auto t1 = std::chrono::steady_clock::now();
+  double t_filter = 0.0, t_rr = 0.0;
+  double *res;
+  if ((st = efe_ws(c, 30, (size_t)N * 8, (void **)&res))) return st;
+  if (s.iter == 0) {
+    if ((st = efe_rayleigh_ritz(c, V, N, ld, lambda, res))) return st;
+  }
+  const int npass = s.iter == 0 ? prm->passes_first : prm->passes;
+  std::vector<double> lh(N);
+  for (int pss = 0; pss < npass; ++pss) {
+    HIPCHK(c, hipMemcpyAsync(lh.data(), lambda, N * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    efe_cheb_params cp{prm->degree, lh[N - 1], b, lh[0], EFE_FILTER_RESIDUAL, prm->prec};
+    auto ta = std::chrono::steady_clock::now();
+    if ((st = efe_cheb_filter(c, V, lambda, N, ld, &cp))) return st;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    t_filter += ms_since(ta);
+    ta = std::chrono::steady_clock::now();
+    if ((st = efe_rayleigh_ritz(c, V, N, ld, lambda, res))) return st;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    t_rr += ms_since(ta);
+  }
+  auto t2 = std::chrono::steady_clock::now();
+  // 3. occupations and output density
+  if (!s.f && (st = efe_alloc(c, (void **)&s.f, 4096 * 8))) return st;
+  if (N > 4096) EFE_FAIL(c, EFE_EINVAL, "more than 4096 vectors");
+  double *fo = s.scal + 8;   // mu, band, TS
+  k_fermi<<<1, 1, 0, c->stream>>>(N, lambda, ne, prm->kT, s.f, fo);
+  std::vector<double> fh(N), fermi(3), resh(N);
+  HIPCHK(c, hipMemcpyAsync(fh.data(), s.f, N * 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(fermi.data(), fo, 3 * 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(resh.data(), res, N * 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  std::vector<int32_t> cols;
+  double max_occ_res = 0.0;
+  for (int j = 0; j < N; ++j)
+    if (fh[j] > 1e-14) {
+      cols.push_back(j);
+      max_occ_res = std::max(max_occ_res, resh[j]);
+    }
+  int32_t *dcols;
+  double *Xh;
+  if ((st = efe_ws(c, 31, std::max<size_t>(cols.size(), 1) * 4, (void **)&dcols))) return st;
+  if ((st = efe_ws(c, 0, (size_t)c->n_nodes * N * 8, (void **)&Xh))) return st;
+  if (!cols.empty())
+    HIPCHK(c, hipMemcpyAsync(dcols, cols.data(), cols.size() * 4, hipMemcpyHostToDevice, c->stream));
+  if ((st = efe_transform_cfe(c, V, ld, Xh, N, N))) return st;
+  {
+    const MeshGeo g = mesh_geo(c);
+    EnrParam e;
+    e.lmax = c->lmax;
+    e.nf = c->nf;
+    e.alpha = c->enr_alpha;
+    e.rc = c->enr_rcut;
+    e.t = c->enr_t;
+    k_density<<<c->n_cells, 256, 0, c->stream>>>(g, e, c->d_xq1, c->d_c2g, c->d_N3, Xh, N,
+                                                 V + c->n_nodes * ld, ld, dcols, (int)cols.size(),
+                                                 s.f, s.cell_ptr, s.cell_atom, c->d_xyz, c->d_nu,
+                                                 s.rho_out);
+    HIPCHK(c, hipGetLastError());
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const double t_dens = ms_since(t2);
+  // 4. energies at rho_out
+  HIPCHK(c, hipMemcpyAsync(s.phi_out, s.phi_rem, c->n_nodes * 8, hipMemcpyDeviceToDevice, c->stream));
+  if ((st = poisson(c, s.rho_out, s.rho_at, s.phi_out, prm->cg_rtol, prm->cg_maxit, &cg_it2)))
+    return st;
+  double *phiq_out;
+  if ((st = efe_ws(c, 32, nq * 8, (void **)&phiq_out))) return st;
+  k_nodes_to_quad<<<c->n_cells, 256, 0, c->stream>>>(c->nloc, c->nqp, c->d_c2g, c->d_N3, s.phi_out,
+                                                     c->d_minv, phiq_out);
+  double *sums = s.scal + 16;
+  HIPCHK(c, hipMemsetAsync(sums, 0, 8 * 8, c->stream));
+  k_energy_sums<<<1024, 256, 0, c->stream>>>(nq, c->nqp, c->d_W3, s.rho_out, s.v_in, s.rho_at,
+                                             s.phi_at, phiq_out, s.v_short, s.rho_in, sums);
+  std::vector<double> sh(7);
+  HIPCHK(c, hipMemcpyAsync(sh.data(), sums, 7 * 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const double E_el = s.e_const + sh[2] + 0.5 * sh[3] + sh[4];
+  const double E = fermi[1] - sh[0] + sh[1] + E_el;
+  rep->E = E;
+  rep->F = E - fermi[2];
+  rep->E_band = fermi[1];
+  rep->E_xc = sh[1];
+  rep->E_el = E_el;
+  rep->mu = fermi[0];
+  rep->n_el = sh[5];
+  rep->drho = sqrt(sh[6]);
+  rep->dE = s.have_E ? E - s.E_prev : 0.0;
+  rep->max_occ_res = max_occ_res;
+  rep->iter = s.iter;
+  rep->passes = npass;
+  rep->cg_iters = cg_it + cg_it2;
+  rep->b = b;
+  rep->t_poisson_ms = t_pois;
+  rep->t_filter_ms = t_filter;
+  rep->t_rr_ms = t_rr;
+  rep->t_density_ms = t_dens;
+  s.E_prev = E;
+  s.have_E = true;
+  // 5. Anderson mixing of rho_in
+  auto t3 = std::chrono::steady_clock::now();
+  const int m = prm->mix_history;
+  if (!s.hist || s.hist_m != m) {
+    if (s.hist) (void)hipFree(s.hist);
+    s.hist = nullptr;
+    if ((st = efe_alloc(c, (void **)&s.hist, (size_t)2 * (m + 1) * nq * 8))) return st;
+    s.hist_m = m;
+    s.nhist = 0;
+  }
+  double *HX = s.hist, *HF = s.hist + (int64_t)(m + 1) * nq;
+  if (s.nhist == m + 1) {   // drop the oldest entry
+    HIPCHK(c, hipMemcpyAsync(HX, HX + nq, (size_t)m * nq * 8, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(HF, HF + nq, (size_t)m * nq * 8, hipMemcpyDeviceToDevice, c->stream));
+    s.nhist = m;
+  }
+  const int k = s.nhist;
+  HIPCHK(c, hipMemcpyAsync(HX + (int64_t)k * nq, s.rho_in, nq * 8, hipMemcpyDeviceToDevice, c->stream));
+  k_sub<<<cdiv(nq, T), T, 0, c->stream>>>(nq, s.rho_out, s.rho_in, HF + (int64_t)k * nq);
+  s.nhist = k + 1;
+  double *gam = s.scal + 32;   // up to 16 coefficients
+  double *A, *dfi, *dfj;
+  if ((st = efe_ws(c, 33, (size_t)(16 * 16 + 16) * 8, (void **)&A))) return st;
+  if ((st = efe_ws(c, 34, (size_t)2 * nq * 8, (void **)&dfi))) return st;
+  dfj = dfi + nq;
+  if (k > 0) {
+    HIPCHK(c, hipMemsetAsync(A, 0, (16 * 16 + 16) * 8, c->stream));
+    double *rhs = A + 16 * 16;
+    const unsigned nb = (unsigned)std::min<int64_t>(cdiv(nq, 256), 1024);
+    for (int i = 0; i < k; ++i) {
+      k_sub<<<cdiv(nq, T), T, 0, c->stream>>>(nq, HF + (int64_t)(i + 1) * nq, HF + (int64_t)i * nq, dfi);
+      k_wdot<<<nb, 256, 0, c->stream>>>(nq, c->nqp, c->d_W3, dfi, HF + (int64_t)k * nq, rhs + i);
+      for (int j = 0; j <= i; ++j) {
+        k_sub<<<cdiv(nq, T), T, 0, c->stream>>>(nq, HF + (int64_t)(j + 1) * nq, HF + (int64_t)j * nq,
+                                                dfj);
+        k_wdot<<<nb, 256, 0, c->stream>>>(nq, c->nqp, c->d_W3, dfi, dfj, A + i * k + j);
+        if (j != i)
+          k_wdot<<<nb, 256, 0, c->stream>>>(nq, c->nqp, c->d_W3, dfi, dfj, A + j * k + i);
+      }
+    }
+    k_small_solve<<<1, 1, 0, c->stream>>>(k, A, rhs, gam);
+  }
+  k_anderson_update<<<cdiv(nq, T), T, 0, c->stream>>>(nq, k, HX, HF, nq, gam, prm->mix_beta,
+                                                      s.rho_in);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  rep->t_other_ms = ms_since(t3);
+  s.iter++;
+  return EFE_OK;
+}

@@ -44,6 +44,24 @@ class ChebParams(ctypes.Structure):
                 ("a_min", ctypes.c_double), ("mode", ctypes.c_int32), ("prec", ctypes.c_int32)]
 
 
+class ScfParams(ctypes.Structure):
+    _fields_ = [("passes_first", ctypes.c_int32), ("passes", ctypes.c_int32),
+                ("degree", ctypes.c_int32), ("prec", ctypes.c_int32), ("kT", ctypes.c_double),
+                ("mix_beta", ctypes.c_double), ("mix_history", ctypes.c_int32),
+                ("cg_rtol", ctypes.c_double), ("cg_maxit", ctypes.c_int32),
+                ("lanczos_steps", ctypes.c_int32)]
+
+
+class ScfReport(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in
+                ("E", "F", "E_band", "E_xc", "E_el", "mu", "n_el", "drho", "dE", "max_occ_res",
+                 "b", "t_poisson_ms", "t_filter_ms", "t_rr_ms", "t_density_ms", "t_other_ms")] + \
+               [("iter", ctypes.c_int32), ("passes", ctypes.c_int32), ("cg_iters", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
 class EFEError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{STATUS.get(status, status)}: {msg}")
@@ -76,6 +94,11 @@ _SIGS = {
                                          ctypes.POINTER(ChebParams)]),
     "efe_rayleigh_ritz": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                            ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]),
+    "efe_set_density": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p]),
+    "efe_get_density": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "efe_scf_step": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                      ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.POINTER(ScfParams), ctypes.POINTER(ScfReport)]),
     "efe_timing": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
     "efe_timing_get": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, c_int64_p, c_double_p]),
     "efe_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
@@ -259,6 +282,41 @@ class Context:
         self._check(lib().efe_rayleigh_ritz(self.h, _ptr(V), n, ld, _ptr(lam),
                                             _ptr(res) if res is not None else None))
         return lam, res
+
+
+    # -------------------------------------------------------------- SCF
+    def set_density(self, rho):
+        self._check(lib().efe_set_density(self.h, _ptr(rho)))
+
+    def get_density(self, which=0):
+        import torch
+        out = torch.empty(self.n_qpts, dtype=torch.float64, device="cuda")
+        self._check(lib().efe_get_density(self.h, int(which), _ptr(out)))
+        return out
+
+    def scf_step(self, V, lam, v0, degree, passes_first=4, passes=1, prec=EFE_FP64,
+                 kT=500 * 3.166811563e-6, mix_beta=0.3, mix_history=8, cg_rtol=1e-12,
+                 cg_maxit=5000, lanczos_steps=20):
+        n, ld = self._block(V)
+        p = ScfParams(int(passes_first), int(passes), int(degree), int(prec), float(kT),
+                      float(mix_beta), int(mix_history), float(cg_rtol), int(cg_maxit),
+                      int(lanczos_steps))
+        rep = ScfReport()
+        self._check(lib().efe_scf_step(self.h, _ptr(V), n, ld, _ptr(lam), _ptr(v0),
+                                       ctypes.byref(p), ctypes.byref(rep)))
+        return rep.as_dict()
+
+
+def scf_run(ctx, V, lam, v0, degree, tol=1e-5, max_iter=50, **kw):
+    """Drive efe_scf_step until |E_k - E_{k-1}| / N_atoms < tol; returns the
+    list of step reports."""
+    hist = []
+    for it in range(max_iter):
+        rep = ctx.scf_step(V, lam, v0, degree, **kw)
+        hist.append(rep)
+        if it > 0 and abs(rep["dE"]) / max(ctx.natoms, 1) < tol:
+            break
+    return hist
 
 
 # module-level names of the C entry points

@@ -1,0 +1,76 @@
+"""GPU SCF (efe_scf_step) against the oracle's SCF on the 2-atom workload:
+same seeded start block, Lanczos start vector and superposition guess on
+both sides; every step's energies, Fermi level and density residual, and the
+first output density element by element."""
+import numpy as np
+import pytest
+
+from paper_2607_06848_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print("[gpu-scf]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def runs():
+    from oracle import enrich, fe, scf
+    from paper_2607_06848_amd import efe
+    w = wl.make("eig2")
+    mesh = fe.Mesh(w["lo"], w["hi"], w["ncell"], w["p"], w["nq"])
+    s = enrich.EFESystem(mesh, w)
+    es = scf.Electrostatics(mesh, w["xyz"], w["Zs"], w)
+    V0 = wl.random_block(s.rows, w["nvec"], 5)
+    v0 = wl.random_vector(s.rows, 7)
+    kT = 500 * scf.KB_HA_PER_K
+    # oracle: first output density by hand (step 0), then the whole run
+    hist, _ = scf.scf(s, es, V0, v0, w["nvec"], w["degree"], 8.0, kT, tol=1e-8, max_iter=30)
+    _say("oracle steps", len(hist), "E", hist[-1]["E"])
+    ctx = efe.Context(w)
+    V = torch.from_numpy(V0).cuda()
+    lam = torch.zeros(w["nvec"], dtype=torch.float64, device="cuda")
+    v0d = torch.from_numpy(v0).cuda()
+    reps, rho1 = [], None
+    for it in range(len(hist)):
+        _say("gpu step", it)
+        reps.append(ctx.scf_step(V, lam, v0d, w["degree"], passes_first=4, passes=1, kT=kT,
+                                 mix_beta=0.3, mix_history=8, cg_rtol=1e-12))
+        if it == 0:
+            rho1 = ctx.get_density(1).cpu().numpy().reshape(mesh.n_cells, mesh.nqp)
+    # the oracle's first output density
+    s2 = enrich.EFESystem(mesh, w)
+    h1, V1 = scf.scf(s2, es, V0, v0, w["nvec"], w["degree"], 8.0, kT, tol=1e-8, max_iter=1)
+    mu, f = scf.fermi_level(h1[0]["lam"], 8.0, kT)
+    rho1_ref = scf.density(s2, V1, f)
+    ctx.close()
+    return hist, reps, rho1, rho1_ref
+
+
+def test_scf_energies_track_oracle(runs):
+    hist, reps, _, _ = runs
+    for h, r in zip(hist, reps):
+        _say(h["iter"], "E", h["E"], r["E"], "dE", r["E"] - h["E"], "mu", r["mu"] - h["mu"])
+        assert abs(r["E"] - h["E"]) < 1e-8
+        assert abs(r["F"] - h["F"]) < 1e-8
+        # the electron count is flat in mu across a gap much wider than kT, so
+        # mu itself is fixed only loosely by the bisection on either side
+        assert abs(r["mu"] - h["mu"]) < 1e-4
+        assert abs(r["n_el"] - h["n_el"]) < 1e-9
+        assert abs(r["drho"] - h["drho"]) < 1e-8 * max(1.0, h["drho"])
+        assert r["cg_iters"] > 0 or h["iter"] == 0
+
+
+def test_first_output_density(runs):
+    _, _, rho1, rho1_ref = runs
+    err = np.abs(rho1 - rho1_ref).max() / np.abs(rho1_ref).max()
+    _say("rho_out rel err", err)
+    assert err < 1e-10
+
+
+def test_scf_converged(runs):
+    hist, reps, _, _ = runs
+    assert abs(reps[-1]["dE"]) / 2 < 1e-8
+    assert reps[-1]["max_occ_res"] < 1e-4
