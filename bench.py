@@ -1,15 +1,20 @@
 """Benchmark of the EFE residual-Chebyshev hot path on one MI355X.
 
-One step = one pass of the hot path over the 64-atom cluster workload
-(16^3 cells, p = 6, 160 vectors, Chebyshev degree 40):
-  rebuild of the potential-dependent operators (cell Hamiltonians, B, H^phiphi),
-  Lanczos spectrum bound, residual Chebyshev filter, Rayleigh-Ritz.
-The headline value is the filter throughput in DoF * vector * degree / s with
-DoF = interior CFE nodes + enrichment rows, averaged over the timed steps.
+One step = one SCF step over the 64-atom cluster workload (16^3 cells, p = 6,
+160 vectors, Chebyshev degree 40): Poisson solve for the electrostatic
+remainder, effective potential, rebuild of the cell Hamiltonians and
+enrichment blocks, Lanczos spectrum bound, residual Chebyshev filter,
+Rayleigh-Ritz, Fermi level, density, energies, Anderson mixing.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c64] [--no-cpu]
+Headline value: filter throughput in DoF * vector * degree / s over the timed
+steps (DoF = interior CFE nodes + enrichment rows; filter time measured
+around efe_cheb_filter inside the step).  Also reported: ms per SCF step,
+time to SCF convergence at 1e-5 Ha/atom from the superposition guess, the
+roofline of the dominant kernel (one colour pass of the cell GEMM, timed with
+HIP events on the library stream) and the CPU oracle on a bounded sample.
 
-Prints one JSON line (rank 0, N = 1 only: this build runs on one GPU).
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec fp64|fp32|bf16]
+                    [--workload c64] [--no-cpu] [--no-scf]
 """
 import argparse
 import json
@@ -23,13 +28,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15, "hbm": 8.0e12}
+PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
 
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(w, seconds_cap=60.0):
+def cpu_baseline(w):
     """The oracle's H^E apply on the same workload with a bounded number of
     vectors (one Chebyshev degree step is one H apply), timed after setup."""
     from oracle import enrich, fe, psp
@@ -64,9 +70,11 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--prec", default="fp64", choices=sorted(PREC))
     ap.add_argument("--workload", default="c64")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-scf", action="store_true", help="skip the time-to-SCF run")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path shards by "
@@ -79,61 +87,55 @@ def main():
 
     w = wl.make(args.workload)
     N, deg = w["nvec"], w["degree"]
-    log("workload", args.workload, "N", N, "degree", deg)
+    prec = PREC[args.prec]
+    log("workload", args.workload, "N", N, "degree", deg, "filter precision", args.prec)
+
+    def new_run():
+        ctx = efe.Context(w)
+        V = torch.from_numpy(wl.random_block(ctx.rows, N, w["v0_seed"])).cuda()
+        lam = torch.zeros(N, dtype=torch.float64, device="cuda")
+        v0 = torch.from_numpy(wl.random_vector(ctx.rows, 7)).cuda()
+        return ctx, V, lam, v0
+
     t0 = time.perf_counter()
-    ctx = efe.Context(w)
-    vq = ctx.local_potential()
-    ctx.set_potential(vq)
+    ctx, V, lam, v0 = new_run()
     torch.cuda.synchronize()
     log(f"setup {time.perf_counter() - t0:.2f} s rows {ctx.rows} dof {ctx.n_dof} "
         f"enr {ctx.n_enr} cells {ctx.n_cells}")
-    V = torch.from_numpy(wl.random_block(ctx.rows, N, w["v0_seed"])).cuda()
-    v0 = torch.from_numpy(wl.random_vector(ctx.rows, 7)).cuda()
-    lam, res = ctx.rayleigh_ritz(V)
-    stream = torch.cuda.current_stream()
-
-    def step(timed):
-        ctx.set_potential(vq)                       # per-SCF operator rebuild
-        b = ctx.spectrum_upper_bound(v0, 20)        # spectrum bound
-        l = lam_box[0].cpu().numpy()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        ctx.cheb_filter(V, lam_box[0], deg, float(l[-1]), b, float(l[0]))
-        e1.record(stream)
-        lam_box[0], res_box[0] = ctx.rayleigh_ritz(V)
-        return e0, e1
-
-    lam_box, res_box = [lam], [res]
+    kw = dict(prec=prec, passes_first=4, passes=1)
     for i in range(args.warmup):
-        step(False)
-        log("warmup step", i, "done")
+        r = ctx.scf_step(V, lam, v0, deg, **kw)
+        log(f"warmup step {i}: E {r['E']:.8f} dE {r['dE']:.2e} filter {r['t_filter_ms']:.0f} ms")
     torch.cuda.synchronize()
     ctx.timing(True)
-    ev = []
+    reps = []
     t0 = time.perf_counter()
     for i in range(args.steps):
-        ev.append(step(True))
+        reps.append(ctx.scf_step(V, lam, v0, deg, **kw))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    filt_ms = [a.elapsed_time(b) for a, b in ev]
     ncell_l, cell_ms = ctx.timing_get("cell")
     napp, app_ms = ctx.timing_get("apply")
     nrr, rr_ms = ctx.timing_get("rr")
     nrec, rec_ms = ctx.timing_get("recur")
     ctx.timing(False)
+    ctx.close()
     ms_step = (t1 - t0) * 1e3 / args.steps
-    filt_s = np.mean(filt_ms) * 1e-3
-    value = ctx.n_dof * N * deg / filt_s
-    log(f"step {ms_step:.1f} ms, filter {np.mean(filt_ms):.1f} ms, applies {napp} "
+    filt_ms = sum(r["t_filter_ms"] for r in reps)
+    npass = sum(r["passes"] for r in reps)
+    value = ctx.n_dof * N * deg * npass / (filt_ms * 1e-3)
+    log(f"step {ms_step:.1f} ms, filter {filt_ms / npass:.1f} ms/pass, applies {napp} "
         f"({app_ms / max(napp, 1):.3f} ms avg), cell launches {ncell_l} "
         f"({cell_ms / max(ncell_l, 1):.3f} ms avg), RR {rr_ms / max(nrr, 1):.1f} ms, "
         f"recurrence {rec_ms / max(nrec, 1):.3f} ms avg")
-    # roofline of the dominant kernel: one colour pass of the FP64 cell GEMM
+    breakdown = {k: float(np.mean([r[k] for r in reps])) for k in
+                 ("t_poisson_ms", "t_filter_ms", "t_rr_ms", "t_density_ms", "t_other_ms")}
+    # roofline of the dominant kernel: one colour pass of the cell GEMM
     cells_per_launch = ctx.n_cells / 8.0
     flops_per_launch = 2.0 * ctx.nloc ** 2 * N * cells_per_launch
     avg_cell_s = cell_ms * 1e-3 / max(ncell_l, 1)
     achieved = flops_per_launch / avg_cell_s
+    peak = PEAK[args.prec]
     out = {
         "metric": "Cheb-filter DoF*vec*deg/s",
         "value": value,
@@ -145,20 +147,35 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": {"fp64": "f64", "fp32": "f32 cell GEMM / f64", "bf16": "bf16 cell GEMM / f64"}[
+            args.prec],
         "data": "synthetic",
         "config": {"workload": f"{w['name']}: {len(w['xyz'])}-atom jittered cubic Gaussian-"
                                f"pseudopotential cluster, {w['ncell'][0]}^3 cells p={w['p']}, "
-                               f"N={N} vectors, Chebyshev degree {deg}, residual filter FP64",
-                   "n_dof": ctx.n_dof, "rows": ctx.rows, "filter_ms": float(np.mean(filt_ms)),
-                   "rr_ms": rr_ms / max(nrr, 1), "h_apply_ms": app_ms / max(napp, 1),
-                   "recurrence_ms": rec_ms / max(nrec, 1)},
-        "roofline": {"bound": "mfma", "kernel": "k_cell_f64 (one colour pass of the cell GEMM)",
-                     "achieved": achieved / 1e12, "peak": PEAK["fp64"] / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK["fp64"], "traffic": None,
+                               f"N={N} vectors, Chebyshev degree {deg}, residual filter, "
+                               f"one SCF step per step",
+                   "n_dof": ctx.n_dof, "rows": ctx.rows, "filter_precision": args.prec,
+                   "filter_ms_per_pass": filt_ms / npass, "rr_ms": rr_ms / max(nrr, 1),
+                   "h_apply_ms": app_ms / max(napp, 1),
+                   "recurrence_ms": rec_ms / max(nrec, 1), "step_breakdown_ms": breakdown},
+        "roofline": {"bound": "mfma", "kernel": "k_cell (one colour pass of the cell GEMM)",
+                     "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None,
                      "launch_ms": avg_cell_s * 1e3, "flops_per_launch": flops_per_launch},
     }
-    ctx.close()
+    if not args.no_scf:
+        log("time to SCF from the superposition guess")
+        ctx, V, lam, v0 = new_run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hist = efe.scf_run(ctx, V, lam, v0, deg, tol=1e-5, max_iter=60, **kw)
+        torch.cuda.synchronize()
+        t_scf = time.perf_counter() - t0
+        ctx.close()
+        out["time_to_scf"] = {"seconds": t_scf, "steps": len(hist), "tol_Ha_per_atom": 1e-5,
+                              "E_Ha": hist[-1]["E"], "converged": abs(hist[-1]["dE"]) /
+                              len(w["xyz"]) < 1e-5, "guess": "superposition of atomic densities"}
+        log(f"SCF: {len(hist)} steps, {t_scf:.1f} s, E {hist[-1]['E']:.8f}")
     if not args.no_cpu:
         log("timing the oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(w)

@@ -120,6 +120,11 @@ efe_status efe_set_potential(efe_ctx *ctx, const double *vq, int32_t precisions)
 
 /* Y = H^E X for ncols vectors (device blocks, rows x ld). */
 efe_status efe_apply_H(efe_ctx *ctx, const double *X, double *Y, int32_t ncols, int64_t ld);
+/* Y = H^E X with the cell GEMMs in the given precision (EFE_FP64, or EFE_FP32
+ * / EFE_BF16 with FP32 accumulation; the matrices must have been built by
+ * efe_set_potential).  The rest of the apply stays FP64. */
+efe_status efe_apply_H_prec(efe_ctx *ctx, const double *X, double *Y, int32_t ncols, int64_t ld,
+                            int32_t prec);
 /* Y = M^E X (exact overlap: diag(m) on CFE rows, M^ee on enrichment rows). */
 efe_status efe_apply_M(efe_ctx *ctx, const double *X, double *Y, int32_t ncols, int64_t ld);
 /* Y = (M~^E)^-1 X (Eq. MEInvApprox). */
@@ -207,6 +212,12 @@ efe_status efe_scf_step(efe_ctx *ctx, double *V, int32_t ncols, int64_t ld, doub
  *   4 whole H apply                      5 whole Rayleigh-Ritz */
 efe_status efe_timing(efe_ctx *ctx, int32_t enable);
 efe_status efe_timing_get(efe_ctx *ctx, int32_t which, int64_t *launches, double *total_ms);
+
+/* Layout check of the matrix-core instructions the cell GEMMs use (test
+ * support): one wave forms D = A B with A 16 x K, B K x 16 (device, FP64,
+ * row-major; K = 4 for which = 0 FP64 and 1 FP32, K = 32 for 2 BF16) through
+ * the lane mappings of the kernels, D 16 x 16 row-major (device). */
+efe_status efe_probe_mfma(int32_t which, const double *A, const double *B, double *D);
 
 /* Message of the last failure on this context ("" if none); with ctx == NULL
  * the message of the last failed efe_setup_mesh on the calling thread. */

@@ -174,10 +174,11 @@ class EFESystem:
             cells = self.supp[I]
             g = mesh.cell_to_global[cells].astype(np.int64)      # (nc, nloc)
             phi, gp = self.phi[I], self.gphi[I]
-            bl = np.einsum('cqk,q,ql->ckl', phi, W, mesh.N3, optimize=True)
-            kl = 0.5 * (np.einsum('cqk,q,ql->ckl', gp[..., 0], W, mesh.Gx, optimize=True)
-                        + np.einsum('cqk,q,ql->ckl', gp[..., 1], W, mesh.Gy, optimize=True)
-                        + np.einsum('cqk,q,ql->ckl', gp[..., 2], W, mesh.Gz, optimize=True))
+            # per cell: (W phi)^T N and 1/2 sum_d (W d_d phi)^T d_d N
+            wphi = (phi * W[None, :, None]).transpose(0, 2, 1)
+            bl = np.matmul(wphi, mesh.N3)
+            kl = 0.5 * sum(np.matmul((gp[..., d] * W[None, :, None]).transpose(0, 2, 1), G)
+                           for d, G in enumerate((mesh.Gx, mesh.Gy, mesh.Gz)))
             kk = np.arange(self.nf)
             rows.append(np.broadcast_to((I * self.nf + kk)[None, :, None], bl.shape).ravel())
             cols.append(np.broadcast_to(g[:, None, :], bl.shape).ravel())
@@ -202,10 +203,13 @@ class EFESystem:
                     continue
                 sI = slice(I * self.nf, (I + 1) * self.nf)
                 sJ = slice(J * self.nf, (J + 1) * self.nf)
-                self.Mpp[sI, sJ] = np.einsum('cqk,q,cql->kl', self.phi[I][iI], W,
-                                             self.phi[J][iJ], optimize=True)
-                self.Hpp_kin[sI, sJ] = 0.5 * np.einsum('cqkd,q,cqld->kl', self.gphi[I][iI], W,
-                                                       self.gphi[J][iJ], optimize=True)
+                # sum over (cell, q) of W phi_Ik phi_Jl (and of grad . grad)
+                wI = (self.phi[I][iI] * W[None, :, None]).reshape(-1, self.nf)
+                self.Mpp[sI, sJ] = wI.T @ self.phi[J][iJ].reshape(-1, self.nf)
+                gI = (self.gphi[I][iI] * W[None, :, None, None]).transpose(0, 1, 3, 2)
+                gJ = self.gphi[J][iJ].transpose(0, 1, 3, 2)
+                self.Hpp_kin[sI, sJ] = 0.5 * (gI.reshape(-1, self.nf).T
+                                              @ gJ.reshape(-1, self.nf))
 
     def _kb(self):
         mesh, p = self.mesh, self.prm
@@ -276,7 +280,8 @@ class EFESystem:
         for I in range(self.natoms):
             cells = self.supp[I]
             wv = W[None, :] * self.vq[cells]
-            vals.append(np.einsum('cqk,cq,ql->ckl', self.phi[I], wv, mesh.N3, optimize=True).ravel())
+            vals.append(np.matmul((self.phi[I] * wv[:, :, None]).transpose(0, 2, 1),
+                                  mesh.N3).ravel())
         rows, cols = self._pattern
         Bv = sp.coo_matrix((np.concatenate(vals), (rows, cols)),
                            shape=(self.n_enr, self.n_nodes)).tocsr() @ sp.diags(self.intr)
@@ -289,8 +294,9 @@ class EFESystem:
                 if common.size == 0:
                     continue
                 wv = W[None, :] * self.vq[common]
-                Hv[I * self.nf:(I + 1) * self.nf, J * self.nf:(J + 1) * self.nf] = np.einsum(
-                    'cqk,cq,cql->kl', self.phi[I][iI], wv, self.phi[J][iJ], optimize=True)
+                wI = (self.phi[I][iI] * wv[:, :, None]).reshape(-1, self.nf)
+                Hv[I * self.nf:(I + 1) * self.nf, J * self.nf:(J + 1) * self.nf] = (
+                    wI.T @ self.phi[J][iJ].reshape(-1, self.nf))
         self.Hpp = self.Hpp_kin + Hv
 
     # ------------------------------------------------------- explicit blocks

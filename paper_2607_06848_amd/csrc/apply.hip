@@ -113,6 +113,128 @@ __global__ __launch_bounds__(256) void k_cell_f64(int ncells, int ntiles,
   }
 }
 
+// FP32 variant: operands converted to FP32 in the gather, v_mfma_f32_16x16x4,
+// FP32 accumulation, FP64 read-modify-write of Y.  FP32 16x16x4 accumulator:
+// register v of lane l holds row 4 (l/16) + v.
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <int NT>
+__global__ __launch_bounds__(256) void k_cell_f32(int ncells, int ntiles,
+                                                  const int32_t *__restrict__ cells,
+                                                  const int32_t *__restrict__ c2g, int nloc,
+                                                  int RB, int KS, const float *__restrict__ Ht,
+                                                  const double *__restrict__ Xh, int64_t ldx,
+                                                  double *__restrict__ Y, int64_t ldy,
+                                                  const double *__restrict__ minv, int ncols) {
+  extern __shared__ float Xf[];   // [KP][NT]
+  const int b = blockIdx.x;
+  const int xcd = b % 8, slot = b / 8;
+  const int ci = (slot / ntiles) * 8 + xcd;
+  const int tile = slot % ntiles;
+  if (ci >= ncells) return;
+  const int cell = cells[ci];
+  const int col0 = tile * NT;
+  const int KP = KS * 4;
+  const int32_t *g = c2g + (int64_t)cell * nloc;
+  for (int idx = threadIdx.x; idx < KP * NT; idx += 256) {
+    const int r = idx / NT, cc = idx % NT;
+    float v = 0.0f;
+    if (r < nloc && col0 + cc < ncols) v = (float)Xh[(int64_t)g[r] * ldx + col0 + cc];
+    Xf[idx] = v;
+  }
+  __syncthreads();
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int li = lane % 16, lk = lane / 16;
+  for (int rb = wave; rb < RB; rb += 4) {
+    v4f acc[NT / 16];
+    for (int cb = 0; cb < NT / 16; ++cb) acc[cb] = (v4f){0.f, 0.f, 0.f, 0.f};
+    const float *hp = Ht + (((int64_t)cell * RB + rb) * KS) * 64 + lane;
+    float a_next = hp[0];
+    for (int ks = 0; ks < KS; ++ks) {
+      const float a = a_next;
+      if (ks + 1 < KS) a_next = hp[(int64_t)(ks + 1) * 64];
+      const float *xr = Xf + (ks * 4 + lk) * NT + li;
+#pragma unroll
+      for (int cb = 0; cb < NT / 16; ++cb)
+        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, xr[cb * 16], acc[cb], 0, 0, 0);
+    }
+    for (int v = 0; v < 4; ++v) {
+      const int row = rb * 16 + 4 * lk + v;
+      if (row >= nloc) continue;
+      const int64_t node = g[row];
+      if (minv[node] == 0.0) continue;
+#pragma unroll
+      for (int cb = 0; cb < NT / 16; ++cb) {
+        const int col = col0 + cb * 16 + li;
+        if (col < ncols) Y[node * ldy + col] += (double)acc[cb][v];
+      }
+    }
+  }
+}
+
+// BF16 variant: v_mfma_f32_16x16x32_bf16, FP32 accumulation.  A operand tile
+// [cell][rb][ks32][lane][8]: lane l holds H[16 rb + l%16][32 ks + 8 (l/16) + e];
+// the gathered block is kept transposed in LDS (XT[col][k]) so that the eight
+// k values of a B operand are one 16-byte read.
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+__device__ inline __bf16 to_bf16(double x) { return (__bf16)(float)x; }
+
+template <int NT>
+__global__ __launch_bounds__(256) void k_cell_bf16(int ncells, int ntiles,
+                                                   const int32_t *__restrict__ cells,
+                                                   const int32_t *__restrict__ c2g, int nloc,
+                                                   int RB, int KS32, const v8bf *__restrict__ Ht,
+                                                   const double *__restrict__ Xh, int64_t ldx,
+                                                   double *__restrict__ Y, int64_t ldy,
+                                                   const double *__restrict__ minv, int ncols) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int KP = KS32 * 32;
+  const int SK = KP + 8;                   // row stride of XT in bf16 elements
+  __bf16 *XT = (__bf16 *)smem;             // [NT][SK]
+  const int b = blockIdx.x;
+  const int xcd = b % 8, slot = b / 8;
+  const int ci = (slot / ntiles) * 8 + xcd;
+  const int tile = slot % ntiles;
+  if (ci >= ncells) return;
+  const int cell = cells[ci];
+  const int col0 = tile * NT;
+  const int32_t *g = c2g + (int64_t)cell * nloc;
+  for (int idx = threadIdx.x; idx < KP * NT; idx += 256) {
+    const int r = idx / NT, cc = idx % NT;
+    double v = 0.0;
+    if (r < nloc && col0 + cc < ncols) v = Xh[(int64_t)g[r] * ldx + col0 + cc];
+    XT[cc * SK + r] = to_bf16(v);
+  }
+  __syncthreads();
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int li = lane % 16, lk = lane / 16;
+  for (int rb = wave; rb < RB; rb += 4) {
+    v4f acc[NT / 16];
+    for (int cb = 0; cb < NT / 16; ++cb) acc[cb] = (v4f){0.f, 0.f, 0.f, 0.f};
+    const v8bf *hp = Ht + (((int64_t)cell * RB + rb) * KS32) * 64 + lane;
+    for (int ks = 0; ks < KS32; ++ks) {
+      const v8bf a = hp[(int64_t)ks * 64];
+#pragma unroll
+      for (int cb = 0; cb < NT / 16; ++cb) {
+        const v8bf bv = *(const v8bf *)(XT + (cb * 16 + li) * SK + ks * 32 + lk * 8);
+        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bv, acc[cb], 0, 0, 0);
+      }
+    }
+    for (int v = 0; v < 4; ++v) {
+      const int row = rb * 16 + 4 * lk + v;
+      if (row >= nloc) continue;
+      const int64_t node = g[row];
+      if (minv[node] == 0.0) continue;
+#pragma unroll
+      for (int cb = 0; cb < NT / 16; ++cb) {
+        const int col = col0 + cb * 16 + li;
+        if (col < ncols) Y[node * ldy + col] += (double)acc[cb][v];
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------------------ projectors
 __global__ __launch_bounds__(256) void k_kb_project(int ncols, const int32_t *__restrict__ kbnode_ptr,
                                                     const int32_t *__restrict__ kbnode,
@@ -240,7 +362,8 @@ efe_status efe_apply_H_internal(efe_ctx *c, const double *XC, int64_t ldx, const
                                 int prec) {
   if (!c->have_potential) EFE_FAIL(c, EFE_ESTATE, "no potential set");
   if (ncols <= 0) return EFE_OK;
-  (void)prec;
+  if ((prec == EFE_FP32 && !c->have32) || (prec == EFE_BF16 && !c->have16))
+    EFE_FAIL(c, EFE_ESTATE, "reduced-precision cell matrices were not built by efe_set_potential");
   efe_status s;
   double *Xh, *W = nullptr;
   const int64_t ldh = ncols;
@@ -265,7 +388,27 @@ efe_status efe_apply_H_internal(efe_ctx *c, const double *XC, int64_t ldx, const
                                              ldh, c->d_Pphi, c->n_enr, XE, lde, c->d_D, W);
   }
   // cell GEMM, colour by colour
-  {
+  if (prec == EFE_FP32 || prec == EFE_BF16) {
+    const int NT = 32;
+    const int ntiles = (int)cdiv(ncols, NT);
+    const size_t shm = prec == EFE_FP32 ? (size_t)c->KP * NT * 4
+                                         : (size_t)NT * (c->KS32 * 32 + 8) * 2;
+    for (int col = 0; col < 8; ++col) {
+      const int nc = c->colour_offsets[col + 1] - c->colour_offsets[col];
+      if (nc == 0) continue;
+      const int64_t nblk = cdiv(nc, 8) * 8 * ntiles;
+      const int t = efe_timer_begin(c, EFE_T_CELL);
+      if (prec == EFE_FP32)
+        k_cell_f32<32><<<nblk, 256, shm, c->stream>>>(
+            nc, ntiles, c->d_colour_order + c->colour_offsets[col], c->d_c2g, c->nloc, c->RB,
+            c->KS, c->d_Htile32, Xh, ldh, Y, ldy, c->d_minv, ncols);
+      else
+        k_cell_bf16<32><<<nblk, 256, shm, c->stream>>>(
+            nc, ntiles, c->d_colour_order + c->colour_offsets[col], c->d_c2g, c->nloc, c->RB,
+            c->KS32, (const v8bf *)c->d_Htile16, Xh, ldh, Y, ldy, c->d_minv, ncols);
+      efe_timer_end(c, EFE_T_CELL, t);
+    }
+  } else {
     const int NT = cell_nt64(c);
     const int ntiles = (int)cdiv(ncols, NT);
     const size_t shm = (size_t)c->KP * NT * 8;
@@ -382,6 +525,15 @@ extern "C" efe_status efe_apply_H(efe_ctx *c, const double *X, double *Y, int32_
   efe_status s = check_block(c, X, Y, ncols, ld);
   if (s) return s;
   return efe_apply_H_internal(c, X, ld, nullptr, X + c->n_nodes * ld, ld, Y, ld, ncols, EFE_FP64);
+}
+
+extern "C" efe_status efe_apply_H_prec(efe_ctx *c, const double *X, double *Y, int32_t ncols,
+                                       int64_t ld, int32_t prec) {
+  efe_status s = check_block(c, X, Y, ncols, ld);
+  if (s) return s;
+  if (prec != EFE_FP64 && prec != EFE_FP32 && prec != EFE_BF16)
+    EFE_FAIL(c, EFE_EINVAL, "bad precision");
+  return efe_apply_H_internal(c, X, ld, nullptr, X + c->n_nodes * ld, ld, Y, ld, ncols, prec);
 }
 
 extern "C" efe_status efe_apply_M(efe_ctx *c, const double *X, double *Y, int32_t ncols,

@@ -91,6 +91,8 @@ struct efe_ctx {
   float *d_Htile32 = nullptr;
   uint16_t *d_Htile16 = nullptr;
   int RB = 0, KS = 0, KP = 0;                          // tile geometry of the cell GEMM
+  int KS32 = 0;                                        // 32-wide k steps of the BF16 tiles
+  bool have32 = false, have16 = false;                 // reduced-precision tiles built
   int cell_nt64 = 0;                                   // column tile of the FP64 cell GEMM
 
   // workspaces (grown on demand)

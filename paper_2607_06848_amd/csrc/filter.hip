@@ -102,7 +102,8 @@ extern "C" efe_status efe_cheb_filter(efe_ctx *c, double *V, const double *lambd
   if (!(prm->a < prm->b) || !(prm->a_min < prm->a)) EFE_FAIL(c, EFE_EINVAL, "need a_min < a < b");
   if (prm->mode != EFE_FILTER_RESIDUAL && prm->mode != EFE_FILTER_STANDARD)
     EFE_FAIL(c, EFE_EINVAL, "bad filter mode");
-  if (prm->prec != EFE_FP64) EFE_FAIL(c, EFE_EINVAL, "filter precision not available");
+  if (prm->prec != EFE_FP64 && prm->prec != EFE_FP32 && prm->prec != EFE_BF16)
+    EFE_FAIL(c, EFE_EINVAL, "bad filter precision");
   if (prm->mode == EFE_FILTER_RESIDUAL && !lambda) EFE_FAIL(c, EFE_EINVAL, "residual mode needs lambda");
   if (!c->have_potential) EFE_FAIL(c, EFE_ESTATE, "no potential set");
   if (ncols == 0) return EFE_OK;
@@ -132,7 +133,7 @@ extern "C" efe_status efe_cheb_filter(efe_ctx *c, double *V, const double *lambd
     double *Yp = nullptr, *Yc = Za, *Yn = Zb;
     for (int k = 1; k <= m; ++k) {
       if ((s = efe_apply_H_internal(c, Yc, ncols, nullptr, Yc + nn * ncols, ncols, W, ncols, ncols,
-                                    EFE_FP64)))
+                                    prm->prec)))
         return s;
       if ((s = efe_enr_block_inv(c, W + nn * ncols, ncols, XE, ncols, ncols))) return s;
       const double a = (k == 1 ? 1.0 : 2.0) * sig[k] / e;
@@ -158,7 +159,8 @@ extern "C" efe_status efe_cheb_filter(efe_ctx *c, double *V, const double *lambd
   k_residual_init<<<nb, T, 0, c->stream>>>(rows, ncols, W, Zb, lambda, sig[1] / e, G, Zc, Zp);
   for (int k = 2; k <= m; ++k) {
     if ((s = efe_enr_block_inv(c, Zc + nn * ncols, ncols, XE, ncols, ncols))) return s;
-    if ((s = efe_apply_H_internal(c, Zc, ncols, c->d_minv, XE, ncols, W, ncols, ncols, EFE_FP64)))
+    // the recurrence's H applies run in the requested precision; G stays FP64
+    if ((s = efe_apply_H_internal(c, Zc, ncols, c->d_minv, XE, ncols, W, ncols, ncols, prm->prec)))
       return s;
     const double a = 2.0 * sig[k] / e;
     const int t = efe_timer_begin(c, EFE_T_RECUR);

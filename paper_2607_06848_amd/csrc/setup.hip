@@ -451,6 +451,25 @@ __global__ __launch_bounds__(256) void k_kb_pphi(MeshGeo g, EnrParam e, double w
               red[0][threadIdx.x] * nu[J * e.nf + threadIdx.x]);
 }
 
+// BF16 operand tiles of v_mfma_f32_16x16x32_bf16 from the FP64 tiles:
+// out[cell][rb][ks32][lane][e] = H[16 rb + lane%16][32 ks32 + 8 (lane/16) + e]
+__global__ void k_tile_bf16(int64_t n_cells, int RB, int KS, int KS32,
+                            const double *__restrict__ H64, uint16_t *__restrict__ out) {
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t total = n_cells * RB * KS32 * 64 * 8;
+  if (idx >= total) return;
+  const int e = idx % 8;
+  const int lane = (idx / 8) % 64;
+  const int ks32 = (idx / 512) % KS32;
+  const int64_t crb = idx / (512 * (int64_t)KS32);      // cell * RB + rb
+  const int i = lane % 16;
+  const int k = 32 * ks32 + 8 * (lane / 16) + e;
+  double v = 0.0;
+  if (k < 4 * KS) v = H64[(crb * KS + k / 4) * 64 + i + 16 * (k % 4)];
+  const __bf16 hb = (__bf16)(float)v;
+  out[idx] = *(const uint16_t *)&hb;
+}
+
 __global__ void k_fill(int64_t n, double v, double *__restrict__ x) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < n) x[i] = v;
@@ -574,6 +593,7 @@ efe_status efe_build_reference(efe_ctx *c) {
   c->KP = (int)cdiv(c->nloc, 4) * 4;
   c->KS = c->KP / 4;
   c->RB = (int)cdiv(c->nloc, 16);
+  c->KS32 = (int)cdiv(c->nloc, 32);
   return EFE_OK;
 }
 
@@ -686,12 +706,20 @@ efe_status efe_build_operators(efe_ctx *c, const double *vq, int precisions) {
   if (!c->d_vq && (s = efe_alloc(c, (void **)&c->d_vq, c->n_qpts * 8))) return s;
   k_copy<<<cdiv(c->n_qpts, 256), 256, 0, c->stream>>>(c->n_qpts, vq, c->d_vq);
   if (!c->d_Htile64 && (s = efe_alloc(c, (void **)&c->d_Htile64, tiles * 8))) return s;
-  const bool want32 = (precisions & (1 << EFE_FP32)) || (precisions & (1 << EFE_BF16));
+  const bool want32 = precisions & (1 << EFE_FP32);
+  const bool want16 = precisions & (1 << EFE_BF16);
   if (want32 && !c->d_Htile32 && (s = efe_alloc(c, (void **)&c->d_Htile32, tiles * 4))) return s;
+  const int64_t tiles16 = c->n_cells * c->RB * c->KS32 * 64 * 8;
+  if (want16 && !c->d_Htile16 && (s = efe_alloc(c, (void **)&c->d_Htile16, tiles16 * 2))) return s;
   const size_t shm = (size_t)c->nqp * 17 * 8;
   k_build_hcell<<<c->n_cells * c->RB, 256, shm, c->stream>>>(
       c->nloc, c->nqp, c->RB, c->KS, c->d_N3, c->d_W3, c->d_K, c->d_vq, c->d_Htile64,
       want32 ? c->d_Htile32 : nullptr);
+  if (want16)
+    k_tile_bf16<<<cdiv(tiles16, 256), 256, 0, c->stream>>>(c->n_cells, c->RB, c->KS, c->KS32,
+                                                           c->d_Htile64, c->d_Htile16);
+  c->have32 = want32;
+  c->have16 = want16;
   if (nf > 0 && c->npairs > 0) {
     const int64_t ns = c->n_snodes * nf;
     k_copy<<<cdiv(ns, 256), 256, 0, c->stream>>>(ns, c->d_Bkin_am, c->d_B_am);

@@ -83,6 +83,8 @@ _SIGS = {
     "efe_set_potential": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]),
     "efe_apply_H": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_int32, ctypes.c_int64]),
+    "efe_apply_H_prec": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_int32, ctypes.c_int64, ctypes.c_int32]),
     "efe_apply_M": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_int32, ctypes.c_int64]),
     "efe_apply_Minv_approx": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
@@ -101,6 +103,8 @@ _SIGS = {
                                       ctypes.POINTER(ScfParams), ctypes.POINTER(ScfReport)]),
     "efe_timing": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
     "efe_timing_get": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, c_int64_p, c_double_p]),
+    "efe_probe_mfma": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p]),
     "efe_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
     "efe_destroy": (None, [ctypes.c_void_p]),
 }
@@ -248,6 +252,12 @@ class Context:
         n, ld = self._block(X)
         Y = self.empty(n, ld) if Y is None else Y
         self._check(lib().efe_apply_H(self.h, _ptr(X), _ptr(Y), n, ld))
+        return Y
+
+    def apply_H_prec(self, X, prec, Y=None):
+        n, ld = self._block(X)
+        Y = self.empty(n, ld) if Y is None else Y
+        self._check(lib().efe_apply_H_prec(self.h, _ptr(X), _ptr(Y), n, ld, int(prec)))
         return Y
 
     def apply_M(self, X, Y=None):
