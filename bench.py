@@ -9,7 +9,8 @@ Rayleigh-Ritz, Fermi level, density, energies, Anderson mixing.
 Headline value: filter throughput in DoF * vector * degree / s over the timed
 steps (DoF = interior CFE nodes + enrichment rows; filter time measured
 around efe_cheb_filter inside the step).  Also reported: ms per SCF step,
-time to SCF convergence at 1e-5 Ha/atom from the superposition guess, the
+time to SCF convergence at 1e-5 Ha/atom in FP64 from the superposition guess
+and with FP32 cell GEMMs from the learned initial density, the
 roofline of the dominant kernel (one colour pass of the cell GEMM, timed with
 HIP events on the library stream) and the CPU oracle on a bounded sample.
 
@@ -74,7 +75,10 @@ def main():
     ap.add_argument("--prec", default="fp64", choices=sorted(PREC))
     ap.add_argument("--workload", default="c64")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-scf", action="store_true", help="skip the time-to-SCF run")
+    ap.add_argument("--no-scf", action="store_true", help="skip the time-to-SCF runs")
+    ap.add_argument("--model", default=os.path.join(ROOT, "paper_2607_06848_amd", "weights",
+                                                    "density_c64.npz"),
+                    help="trained initial-density network for the mixed + learned SCF run")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path shards by "
@@ -164,18 +168,38 @@ def main():
                      "launch_ms": avg_cell_s * 1e3, "flops_per_launch": flops_per_launch},
     }
     if not args.no_scf:
-        log("time to SCF from the superposition guess")
-        ctx, V, lam, v0 = new_run()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        hist = efe.scf_run(ctx, V, lam, v0, deg, tol=1e-5, max_iter=60, **kw)
-        torch.cuda.synchronize()
-        t_scf = time.perf_counter() - t0
-        ctx.close()
-        out["time_to_scf"] = {"seconds": t_scf, "steps": len(hist), "tol_Ha_per_atom": 1e-5,
-                              "E_Ha": hist[-1]["E"], "converged": abs(hist[-1]["dE"]) /
-                              len(w["xyz"]) < 1e-5, "guess": "superposition of atomic densities"}
-        log(f"SCF: {len(hist)} steps, {t_scf:.1f} s, E {hist[-1]['E']:.8f}")
+        from paper_2607_06848_amd import learned
+        runs = [("fp64_sad", PREC["fp64"], None)]
+        model = None
+        if os.path.exists(args.model):
+            model = learned.Model.load(args.model)
+            runs.append(("fp32_learned", PREC["fp32"], model))
+        else:
+            log(f"no density model at {args.model}: only the superposition-guess run")
+        res = {}
+        for name, prec_k, mdl in runs:
+            log(f"time to SCF: {name}")
+            ctx, V, lam, v0 = new_run()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fb, fac = mdl.apply(ctx) if mdl is not None else ctx.density_guess(None)
+            hist = efe.scf_run(ctx, V, lam, v0, deg, tol=1e-5, max_iter=60, prec=prec_k,
+                               passes_first=4, passes=1)
+            torch.cuda.synchronize()
+            t_scf = time.perf_counter() - t0
+            ctx.close()
+            res[name] = {"seconds": t_scf, "steps": len(hist),
+                         "filter_passes": sum(h["passes"] for h in hist), "E_Ha": hist[-1]["E"],
+                         "converged": abs(hist[-1]["dE"]) / len(w["xyz"]) < 1e-5,
+                         "guess": "learned" if mdl is not None and not fb else "superposition",
+                         "filter_precision": "fp64" if prec_k == 0 else "fp32"}
+            log(f"SCF {name}: {len(hist)} steps, {t_scf:.1f} s, E {hist[-1]['E']:.8f}")
+        if "fp32_learned" in res:
+            a, b = res["fp64_sad"], res["fp32_learned"]
+            res["speedup"] = a["seconds"] / b["seconds"]
+            res["dE_per_atom"] = abs(a["E_Ha"] - b["E_Ha"]) / len(w["xyz"])
+        res["tol_Ha_per_atom"] = 1e-5
+        out["time_to_scf"] = res
     if not args.no_cpu:
         log("timing the oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(w)

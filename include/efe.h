@@ -195,6 +195,62 @@ efe_status efe_set_density(efe_ctx *ctx, const double *rho_q);
 /* Copy a density (device, n_qpts): which = 0 input of the next step, 1 output
  * of the last step, 2 superposition of atomic densities. */
 efe_status efe_get_density(efe_ctx *ctx, int32_t which, double *out);
+/* Gauss points of the mesh (Sec. III.A: n_q-point rule per cell), in the
+ * order every per-point array uses (cell by cell, x fastest inside a cell):
+ * xq (device, n_qpts x 3) positions, wq (device, n_qpts) weights including the
+ * cell Jacobian.  Either output may be NULL, not both (EFE_EINVAL). */
+efe_status efe_get_quadrature(efe_ctx *ctx, double *xq, double *wq);
+
+/* ---------------------------------------------------------------------------
+ * Learned initial density.  The paper starts the SCF from atomic densities
+ * (Sec. IV); this component proposes a corrected start and leaves the
+ * converged answer to the SCF.  A point's 25 features are the power spectrum
+ * P_nl = sum_m (sum_I g_n(d_I) Y_lm(u_I))^2 of its 16 nearest atoms (ties by
+ * the lower atom index; g_n(d) = exp(-(d - n)^2 / 2), n = 0..7; real spherical
+ * harmonics l = 0..2; feature 3n + l) and log(max(rho_SAD, 1e-12)) (feature
+ * 24), standardized as (f - shift) / scale.  The network is
+ * 25 -> 128 -> 128 -> 128 -> 1 with SiLU, FP32, parameters in one flat array
+ * of efe_mlp_num_params() floats: W1 [128][25], b1 [128], W2 [128][128], b2,
+ * W3 [128][128], b3, W4 [128], b4 [1], row-major.  These calls take no
+ * context: `stream` is a hipStream_t (NULL: the default stream), all arrays
+ * are device arrays owned by the caller, and errors are reported by status
+ * with the message in efe_last_error(NULL).  EFE_EINVAL is returned for
+ * negative sizes or missing arrays before any launch.
+ * ------------------------------------------------------------------------- */
+int64_t efe_mlp_num_params(void);
+/* feat (npts x 25, FP32, row per point) of the points pts (npts x 3) around
+ * the atoms xyz (natoms x 3) with SAD densities rho_sad (npts).  shift and
+ * scale (25 each) are both NULL (raw features) or both given. */
+efe_status efe_descriptors(void *stream, const double *pts, int64_t npts, const double *xyz,
+                           int32_t natoms, const double *rho_sad, const float *shift,
+                           const float *scale, float *feat);
+/* out (npts) = network(feat).  acts (3 x npts x 128, optional) receives the
+ * pre-activations of the three hidden layers for efe_mlp_backward. */
+efe_status efe_mlp_forward(void *stream, const float *params, const float *feat, int64_t npts,
+                           float *out, float *acts);
+/* Quadrature-weighted squared error L = sum w (out - target)^2 / sum w:
+ * dout = dL/dout, sums (2 doubles) = {sum w, sum w (out - target)^2}. */
+efe_status efe_mlp_loss_grad(void *stream, const float *out, const float *target,
+                             const float *weight, int64_t npts, float *dout, double *sums);
+/* grads (efe_mlp_num_params floats, overwritten) = d(sum dout * out)/dparams
+ * for the batch whose forward pass stored acts; work: 2 x npts x 128 floats. */
+efe_status efe_mlp_backward(void *stream, const float *params, const float *feat,
+                            const float *acts, const float *dout, int64_t npts, float *grads,
+                            float *work);
+/* One Adam step (step counts from 1) on n parameters with moments m, v:
+ * m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+ * params -= lr (m / (1-b1^step)) / (sqrt(v / (1-b2^step)) + eps). */
+efe_status efe_mlp_adam(void *stream, float *params, const float *grads, float *m, float *v,
+                        int64_t n, double lr, double beta1, double beta2, double eps, int64_t step);
+/* Set the next SCF step's input density to the learned guess
+ * rho_0 = max(rho_SAD + s_t * network, 0) scaled to the electron count
+ * sum_I Z_I, on the context's Gauss points; resets the mixing history.
+ * norm (host, 51 floats) = shift[25], scale[25], s_t.  Falls back to rho_SAD
+ * (and reports *used_fallback = 1) when params is NULL, a value is not
+ * finite, or the scale factor leaves [0.9, 1.1]; *factor (host) is that
+ * factor (NaN for non-finite values).  Synchronizes the stream. */
+efe_status efe_density_guess(efe_ctx *ctx, const float *params, const float *norm,
+                             int32_t *used_fallback, double *factor);
 /* One SCF step.  V (rows x ld, device) holds the N-vector subspace: any block
  * before the first step (it is Rayleigh-Ritz orthonormalized first), the Ritz
  * vectors after each step; lambda (device, N) their values; v0 (device, rows)

@@ -51,122 +51,143 @@ __global__ __launch_bounds__(256) void k_pre(int64_t n_nodes, int ncols, const d
 }
 
 // ------------------------------------------------------------------ cell GEMM
-// One block = one cell of the current colour and NT columns.  The gathered
-// 16-row-padded block Xh_cell (KP x NT) sits in LDS; each wave streams the
-// pre-tiled cell matrix rows (one 512-byte operand load per MFMA k-step) and
-// accumulates 16 x NT output tiles with v_mfma_f64_16x16x4.  Results are
-// added to Y on interior nodes; cells of one colour share no node, so the
-// read-modify-write needs no atomics.  blockIdx -> (cell, tile) keeps all
-// column tiles of a cell on one XCD (blocks are dealt round-robin over 8).
-template <int NT>
-__global__ __launch_bounds__(256) void k_cell_f64(int ncells, int ntiles,
-                                                  const int32_t *__restrict__ cells,
-                                                  const int32_t *__restrict__ c2g, int nloc,
-                                                  int RB, int KS, const double *__restrict__ Ht,
-                                                  const double *__restrict__ Xh, int64_t ldx,
-                                                  double *__restrict__ Y, int64_t ldy,
-                                                  const double *__restrict__ minv, int ncols) {
-  extern __shared__ double Xs[];   // [KP][NT]
-  const int b = blockIdx.x;
-  const int xcd = b % 8, slot = b / 8;
-  const int ci = (slot / ntiles) * 8 + xcd;
-  const int tile = slot % ntiles;
-  if (ci >= ncells) return;
-  const int cell = cells[ci];
-  const int col0 = tile * NT;
-  const int KP = KS * 4;
-  const int32_t *g = c2g + (int64_t)cell * nloc;
-  for (int idx = threadIdx.x; idx < KP * NT; idx += 256) {
-    const int r = idx / NT, cc = idx % NT;
-    double v = 0.0;
-    if (r < nloc && col0 + cc < ncols) v = Xh[(int64_t)g[r] * ldx + col0 + cc];
-    Xs[idx] = v;
+// Cell GEMM, second form: one work-group = one cell of the colour and a
+// part of its row blocks, all (up to 160) columns.  Each wave keeps RBW row
+// blocks x CBM column blocks of accumulators, so every cell-matrix fragment
+// loaded from memory feeds CBM MFMAs.  The gathered block of Xh streams
+// through LDS in 16-row chunks, double buffered; the cell-matrix fragments
+// of the next chunk are loaded into registers while the current chunk is
+// multiplied.  T = double (v_mfma_f64_16x16x4) or float
+// (v_mfma_f32_16x16x4, FP32 accumulation).
+template <typename T>
+struct CellMfma;
+template <>
+struct CellMfma<double> {
+  typedef v4d acc_t;
+  static constexpr int NCP = 176;   // LDS row stride: two 16-lane rows hit disjoint banks
+  __device__ static inline acc_t op(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
-  __syncthreads();
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  const int li = lane % 16, lk = lane / 16;
-  for (int rb = wave; rb < RB; rb += 4) {
-    v4d acc[NT / 16];
-    for (int cb = 0; cb < NT / 16; ++cb) acc[cb] = (v4d){0.0, 0.0, 0.0, 0.0};
-    const double *hp = Ht + (((int64_t)cell * RB + rb) * KS) * 64 + lane;
-    double a_next = hp[0];
-    for (int ks = 0; ks < KS; ++ks) {
-      const double a = a_next;
-      if (ks + 1 < KS) a_next = hp[(int64_t)(ks + 1) * 64];
-      const double *xr = Xs + (ks * 4 + lk) * NT + li;
-#pragma unroll
-      for (int cb = 0; cb < NT / 16; ++cb)
-        acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, xr[cb * 16], acc[cb], 0, 0, 0);
-    }
-    // FP64 16x16x4 accumulator: register v of lane l holds row 4 v + l/16
-    for (int v = 0; v < 4; ++v) {
-      const int row = rb * 16 + 4 * v + lk;
-      if (row >= nloc) continue;
-      const int64_t node = g[row];
-      if (minv[node] == 0.0) continue;
-#pragma unroll
-      for (int cb = 0; cb < NT / 16; ++cb) {
-        const int col = col0 + cb * 16 + li;
-        if (col < ncols) Y[node * ldy + col] += acc[cb][v];
-      }
-    }
-  }
-}
-
-// FP32 variant: operands converted to FP32 in the gather, v_mfma_f32_16x16x4,
-// FP32 accumulation, FP64 read-modify-write of Y.  FP32 16x16x4 accumulator:
-// register v of lane l holds row 4 (l/16) + v.
+  // accumulator register v of lane l holds row 4 v + l/16
+  __device__ static inline int row(int v, int lk) { return 4 * v + lk; }
+};
 typedef float v4f __attribute__((ext_vector_type(4)));
+template <>
+struct CellMfma<float> {
+  typedef v4f acc_t;
+  static constexpr int NCP = 208;   // four 16-lane rows on disjoint banks
+  __device__ static inline acc_t op(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // accumulator register v of lane l holds row 4 (l/16) + v
+  __device__ static inline int row(int v, int lk) { return 4 * lk + v; }
+};
 
-template <int NT>
-__global__ __launch_bounds__(256) void k_cell_f32(int ncells, int ntiles,
-                                                  const int32_t *__restrict__ cells,
-                                                  const int32_t *__restrict__ c2g, int nloc,
-                                                  int RB, int KS, const float *__restrict__ Ht,
-                                                  const double *__restrict__ Xh, int64_t ldx,
-                                                  double *__restrict__ Y, int64_t ldy,
-                                                  const double *__restrict__ minv, int ncols) {
-  extern __shared__ float Xf[];   // [KP][NT]
+constexpr int CELL_CBM = 10;   // column blocks per launch (160 columns)
+
+template <typename T, int RBW>
+__global__ __launch_bounds__(256) void k_cell2(int ncells, int nparts,
+                                               const int32_t *__restrict__ cells,
+                                               const int32_t *__restrict__ c2g, int nloc, int RB,
+                                               int KS, const T *__restrict__ Ht,
+                                               const double *__restrict__ Xh, int64_t ldx,
+                                               double *__restrict__ Y, int64_t ldy,
+                                               const double *__restrict__ minv, int ncols) {
+  typedef CellMfma<T> M;
+  typedef typename M::acc_t acc_t;
+  constexpr int CBM = CELL_CBM, NC = CBM * 16, KC = 16, EPT = KC * NC / 256;
+  __shared__ T Xs[2][KC][M::NCP];
   const int b = blockIdx.x;
   const int xcd = b % 8, slot = b / 8;
-  const int ci = (slot / ntiles) * 8 + xcd;
-  const int tile = slot % ntiles;
+  const int ci = (slot / nparts) * 8 + xcd;
+  const int part = slot % nparts;
   if (ci >= ncells) return;
   const int cell = cells[ci];
-  const int col0 = tile * NT;
-  const int KP = KS * 4;
   const int32_t *g = c2g + (int64_t)cell * nloc;
-  for (int idx = threadIdx.x; idx < KP * NT; idx += 256) {
-    const int r = idx / NT, cc = idx % NT;
-    float v = 0.0f;
-    if (r < nloc && col0 + cc < ncols) v = (float)Xh[(int64_t)g[r] * ldx + col0 + cc];
-    Xf[idx] = v;
-  }
-  __syncthreads();
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  const int li = lane % 16, lk = lane / 16;
-  for (int rb = wave; rb < RB; rb += 4) {
-    v4f acc[NT / 16];
-    for (int cb = 0; cb < NT / 16; ++cb) acc[cb] = (v4f){0.f, 0.f, 0.f, 0.f};
-    const float *hp = Ht + (((int64_t)cell * RB + rb) * KS) * 64 + lane;
-    float a_next = hp[0];
-    for (int ks = 0; ks < KS; ++ks) {
-      const float a = a_next;
-      if (ks + 1 < KS) a_next = hp[(int64_t)(ks + 1) * 64];
-      const float *xr = Xf + (ks * 4 + lk) * NT + li;
+  const int t = threadIdx.x, wave = t / 64, lane = t % 64, li = lane % 16, lk = lane / 16;
+  const int rbase = (part * 4 + wave) * RBW;
+  const int CB = (ncols + 15) / 16;
+  const int NCH = (KS + 3) / 4;
+  const T *hp = Ht + ((int64_t)cell * RB) * KS * 64 + lane;
+
+  T xr[EPT];
+  T a0[4][RBW], a1[4][RBW];
+  acc_t acc[RBW][CBM];
 #pragma unroll
-      for (int cb = 0; cb < NT / 16; ++cb)
-        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, xr[cb * 16], acc[cb], 0, 0, 0);
+  for (int r = 0; r < RBW; ++r)
+#pragma unroll
+    for (int cb = 0; cb < CBM; ++cb) acc[r][cb] = (acc_t){0, 0, 0, 0};
+
+  auto stage_load = [&](int ch) {
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      const int idx = t + 256 * j, r = idx / NC, cc = idx % NC, k = ch * KC + r;
+      xr[j] = (k < nloc && cc < ncols) ? (T)Xh[(int64_t)g[k] * ldx + cc] : (T)0;
     }
+  };
+  auto stage_store = [&](int buf) {
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      const int idx = t + 256 * j;
+      Xs[buf][idx / NC][idx % NC] = xr[j];
+    }
+  };
+  auto a_load = [&](int ch, T (&dst)[4][RBW]) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int r = 0; r < RBW; ++r) {
+        const int ks = ch * 4 + s, rb = rbase + r;
+        dst[s][r] = (ks < KS && rb < RB) ? hp[((int64_t)rb * KS + ks) * 64] : (T)0;
+      }
+  };
+  auto compute = [&](int buf, const T (&src)[4][RBW], int ch) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      if (ch * 4 + s >= KS) break;
+      T bv[CBM];
+#pragma unroll
+      for (int cb = 0; cb < CBM; ++cb) bv[cb] = Xs[buf][s * 4 + lk][cb * 16 + li];
+#pragma unroll
+      for (int r = 0; r < RBW; ++r)
+#pragma unroll
+        for (int cb = 0; cb < CBM; ++cb)
+          if (cb < CB) acc[r][cb] = M::op(src[s][r], bv[cb], acc[r][cb]);
+    }
+  };
+  auto step = [&](int ch, const T (&cur)[4][RBW], T (&nxt)[4][RBW], int buf) {
+    const bool more = ch + 1 < NCH;
+    if (more) {
+      stage_load(ch + 1);
+      a_load(ch + 1, nxt);
+    }
+    compute(buf, cur, ch);
+    if (more) stage_store(buf ^ 1);
+    __syncthreads();
+  };
+
+  stage_load(0);
+  a_load(0, a0);
+  stage_store(0);
+  __syncthreads();
+  for (int ch = 0; ch < NCH; ch += 2) {
+    step(ch, a0, a1, 0);
+    if (ch + 1 < NCH) step(ch + 1, a1, a0, 1);
+  }
+#pragma unroll
+  for (int r = 0; r < RBW; ++r) {
+    const int rb = rbase + r;
+    if (rb >= RB) continue;
+#pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int row = rb * 16 + 4 * lk + v;
+      const int row = rb * 16 + M::row(v, lk);
       if (row >= nloc) continue;
       const int64_t node = g[row];
       if (minv[node] == 0.0) continue;
 #pragma unroll
-      for (int cb = 0; cb < NT / 16; ++cb) {
-        const int col = col0 + cb * 16 + li;
-        if (col < ncols) Y[node * ldy + col] += (double)acc[cb][v];
+      for (int cb = 0; cb < CBM; ++cb) {
+        const int col = cb * 16 + li;
+        if (cb < CB && col < ncols) Y[node * ldy + col] += (double)acc[r][cb][v];
       }
     }
   }
@@ -338,23 +359,24 @@ __global__ void k_enr_block_apply(int natoms, int nf, int ncols, const double *_
 }
 
 // ------------------------------------------------------------------ launchers
-// Column tile of the FP64 cell GEMM: 32 columns need 88 KB of LDS at p = 6,
-// which needs the dynamic-LDS limit raised above 64 KB; 16 otherwise.
-static int cell_nt64(efe_ctx *c) {
-  if (c->cell_nt64 == 0) {
-    const size_t shm32 = (size_t)c->KP * 32 * 8;
-    c->cell_nt64 = 16;
-    if (shm32 <= 64 * 1024) {
-      c->cell_nt64 = 32;
-    } else if (hipFuncSetAttribute((const void *)k_cell_f64<32>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)shm32) == hipSuccess) {
-      c->cell_nt64 = 32;
-    } else {
-      (void)hipGetLastError();
+// Colour passes of the cell GEMM in column chunks of 160.
+template <typename T, int RBW>
+static void launch_cell2(efe_ctx *c, const T *Ht, const double *Xh, int64_t ldh, double *Y,
+                         int64_t ldy, int ncols) {
+  const int nparts = (int)cdiv(c->RB, 4 * RBW);
+  for (int col0 = 0; col0 < ncols; col0 += 16 * CELL_CBM) {
+    const int nch = std::min(16 * CELL_CBM, ncols - col0);
+    for (int col = 0; col < 8; ++col) {
+      const int nc = c->colour_offsets[col + 1] - c->colour_offsets[col];
+      if (nc == 0) continue;
+      const int64_t nblk = cdiv(nc, 8) * 8 * nparts;
+      const int t = efe_timer_begin(c, EFE_T_CELL);
+      k_cell2<T, RBW><<<nblk, 256, 0, c->stream>>>(
+          nc, nparts, c->d_colour_order + c->colour_offsets[col], c->d_c2g, c->nloc, c->RB, c->KS,
+          Ht, Xh + col0, ldh, Y + col0, ldy, c->d_minv, nch);
+      efe_timer_end(c, EFE_T_CELL, t);
     }
   }
-  return c->cell_nt64;
 }
 
 efe_status efe_apply_H_internal(efe_ctx *c, const double *XC, int64_t ldx, const double *scale,
@@ -388,43 +410,22 @@ efe_status efe_apply_H_internal(efe_ctx *c, const double *XC, int64_t ldx, const
                                              ldh, c->d_Pphi, c->n_enr, XE, lde, c->d_D, W);
   }
   // cell GEMM, colour by colour
-  if (prec == EFE_FP32 || prec == EFE_BF16) {
+  if (prec == EFE_FP64) {
+    launch_cell2<double, 2>(c, c->d_Htile64, Xh, ldh, Y, ldy, ncols);
+  } else if (prec == EFE_FP32) {
+    launch_cell2<float, 3>(c, c->d_Htile32, Xh, ldh, Y, ldy, ncols);
+  } else {
     const int NT = 32;
     const int ntiles = (int)cdiv(ncols, NT);
-    const size_t shm = prec == EFE_FP32 ? (size_t)c->KP * NT * 4
-                                         : (size_t)NT * (c->KS32 * 32 + 8) * 2;
+    const size_t shm = (size_t)NT * (c->KS32 * 32 + 8) * 2;
     for (int col = 0; col < 8; ++col) {
       const int nc = c->colour_offsets[col + 1] - c->colour_offsets[col];
       if (nc == 0) continue;
       const int64_t nblk = cdiv(nc, 8) * 8 * ntiles;
       const int t = efe_timer_begin(c, EFE_T_CELL);
-      if (prec == EFE_FP32)
-        k_cell_f32<32><<<nblk, 256, shm, c->stream>>>(
-            nc, ntiles, c->d_colour_order + c->colour_offsets[col], c->d_c2g, c->nloc, c->RB,
-            c->KS, c->d_Htile32, Xh, ldh, Y, ldy, c->d_minv, ncols);
-      else
-        k_cell_bf16<32><<<nblk, 256, shm, c->stream>>>(
+      k_cell_bf16<32><<<nblk, 256, shm, c->stream>>>(
             nc, ntiles, c->d_colour_order + c->colour_offsets[col], c->d_c2g, c->nloc, c->RB,
             c->KS32, (const v8bf *)c->d_Htile16, Xh, ldh, Y, ldy, c->d_minv, ncols);
-      efe_timer_end(c, EFE_T_CELL, t);
-    }
-  } else {
-    const int NT = cell_nt64(c);
-    const int ntiles = (int)cdiv(ncols, NT);
-    const size_t shm = (size_t)c->KP * NT * 8;
-    for (int col = 0; col < 8; ++col) {
-      const int nc = c->colour_offsets[col + 1] - c->colour_offsets[col];
-      if (nc == 0) continue;
-      const int64_t nblk = cdiv(nc, 8) * 8 * ntiles;
-      const int t = efe_timer_begin(c, EFE_T_CELL);
-      if (NT == 32)
-        k_cell_f64<32><<<nblk, 256, shm, c->stream>>>(
-            nc, ntiles, c->d_colour_order + c->colour_offsets[col], c->d_c2g, c->nloc, c->RB,
-            c->KS, c->d_Htile64, Xh, ldh, Y, ldy, c->d_minv, ncols);
-      else
-        k_cell_f64<16><<<nblk, 256, shm, c->stream>>>(
-            nc, ntiles, c->d_colour_order + c->colour_offsets[col], c->d_c2g, c->nloc, c->RB,
-            c->KS, c->d_Htile64, Xh, ldh, Y, ldy, c->d_minv, ncols);
       efe_timer_end(c, EFE_T_CELL, t);
     }
   }

@@ -53,6 +53,8 @@ static efe_status upload(efe_ctx *ctx, T **dst, const std::vector<T> &src) {
 // message of the last failed efe_setup_mesh on this thread
 static thread_local std::string g_setup_error;
 
+void efe_set_global_error(const std::string &msg) { g_setup_error = msg; }
+
 // --------------------------------------------------------------- mesh tables
 static void build_mesh_tables(efe_ctx *c) {
   const int P = c->P, p = c->p;

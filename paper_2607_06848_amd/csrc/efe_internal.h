@@ -93,7 +93,6 @@ struct efe_ctx {
   int RB = 0, KS = 0, KP = 0;                          // tile geometry of the cell GEMM
   int KS32 = 0;                                        // 32-wide k steps of the BF16 tiles
   bool have32 = false, have16 = false;                 // reduced-precision tiles built
-  int cell_nt64 = 0;                                   // column tile of the FP64 cell GEMM
 
   // workspaces (grown on demand)
   std::vector<DevBuf> ws;
@@ -124,6 +123,8 @@ struct efe_ctx {
   } while (0)
 
 efe_status efe_alloc(efe_ctx *ctx, void **p, size_t bytes);
+// message returned by efe_last_error(NULL) (calls that take no context)
+void efe_set_global_error(const std::string &msg);
 // workspace slot `slot` of at least `bytes` bytes (kept across calls)
 efe_status efe_ws(efe_ctx *ctx, int slot, size_t bytes, void **p);
 

@@ -98,6 +98,26 @@ _SIGS = {
                                            ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]),
     "efe_set_density": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p]),
     "efe_get_density": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "efe_get_quadrature": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "efe_mlp_num_params": (ctypes.c_int64, []),
+    "efe_descriptors": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                         ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "efe_mlp_forward": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]),
+    "efe_mlp_loss_grad": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                           ctypes.c_void_p]),
+    "efe_mlp_backward": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                          ctypes.c_void_p, ctypes.c_void_p]),
+    "efe_mlp_adam": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                      ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_double, ctypes.c_int64]),
+    "efe_density_guess": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.POINTER(ctypes.c_float), c_int32_p,
+                                           ctypes.POINTER(ctypes.c_double)]),
     "efe_scf_step": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                       ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                       ctypes.POINTER(ScfParams), ctypes.POINTER(ScfReport)]),
@@ -304,6 +324,29 @@ class Context:
         self._check(lib().efe_get_density(self.h, int(which), _ptr(out)))
         return out
 
+    def density_guess(self, params=None, norm=None):
+        """Set the next step's input density to the learned guess (SAD when
+        params is None); returns (used_fallback, factor)."""
+        fb = ctypes.c_int32()
+        fac = ctypes.c_double()
+        nm = None
+        if params is not None:
+            arr = np.ascontiguousarray(np.asarray(norm, np.float32).ravel())
+            if arr.size != 51:
+                raise ValueError("norm holds shift[25], scale[25], target scale")
+            nm = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+        self._check(lib().efe_density_guess(self.h, _ptr(params) if params is not None else None,
+                                            nm, ctypes.byref(fb), ctypes.byref(fac)))
+        return bool(fb.value), fac.value
+
+    def quadrature(self):
+        """(positions (n_qpts, 3), weights (n_qpts,)) of the Gauss points."""
+        import torch
+        xq = torch.empty(self.n_qpts, 3, dtype=torch.float64, device="cuda")
+        wq = torch.empty(self.n_qpts, dtype=torch.float64, device="cuda")
+        self._check(lib().efe_get_quadrature(self.h, _ptr(xq), _ptr(wq)))
+        return xq, wq
+
     def scf_step(self, V, lam, v0, degree, passes_first=4, passes=1, prec=EFE_FP64,
                  kT=500 * 3.166811563e-6, mix_beta=0.3, mix_history=8, cg_rtol=1e-12,
                  cg_maxit=5000, lanczos_steps=20):
@@ -327,6 +370,76 @@ def scf_run(ctx, V, lam, v0, degree, tol=1e-5, max_iter=50, **kw):
         if it > 0 and abs(rep["dE"]) / max(ctx.natoms, 1) < tol:
             break
     return hist
+
+
+# ------------------------------------------------------------------ learned density
+def _stream(stream):
+    import torch
+    return ctypes.c_void_p(stream if stream is not None else
+                           torch.cuda.current_stream().cuda_stream)
+
+
+def _gcheck(st, what):
+    if st != 0:
+        raise EFEError(st, f"{what}: " + (lib().efe_last_error(None) or b"").decode())
+
+
+def mlp_num_params():
+    return int(lib().efe_mlp_num_params())
+
+
+def efe_descriptors(pts, xyz, rho_sad, shift=None, scale=None, out=None, stream=None):
+    """(npts, 25) FP32 features; pts (npts, 3), xyz (natoms, 3), rho_sad (npts)
+    are FP64 device tensors, shift/scale FP32 device tensors or None."""
+    import torch
+    n = pts.shape[0]
+    if out is None:
+        out = torch.empty(n, 25, dtype=torch.float32, device=pts.device)
+    _gcheck(lib().efe_descriptors(_stream(stream), _ptr(pts), n, _ptr(xyz), xyz.shape[0],
+                                  _ptr(rho_sad), _ptr(shift) if shift is not None else None,
+                                  _ptr(scale) if scale is not None else None, _ptr(out)),
+            "efe_descriptors")
+    return out
+
+
+def efe_mlp_forward(params, feat, acts=None, out=None, stream=None):
+    import torch
+    n = feat.shape[0]
+    if out is None:
+        out = torch.empty(n, dtype=torch.float32, device=feat.device)
+    _gcheck(lib().efe_mlp_forward(_stream(stream), _ptr(params), _ptr(feat), n, _ptr(out),
+                                  _ptr(acts) if acts is not None else None), "efe_mlp_forward")
+    return out
+
+
+def efe_mlp_loss_grad(out, target, weight, dout=None, sums=None, stream=None):
+    import torch
+    n = out.shape[0]
+    if dout is None:
+        dout = torch.empty_like(out)
+    if sums is None:
+        sums = torch.empty(2, dtype=torch.float64, device=out.device)
+    _gcheck(lib().efe_mlp_loss_grad(_stream(stream), _ptr(out), _ptr(target), _ptr(weight), n,
+                                    _ptr(dout), _ptr(sums)), "efe_mlp_loss_grad")
+    return dout, sums
+
+
+def efe_mlp_backward(params, feat, acts, dout, grads=None, work=None, stream=None):
+    import torch
+    n = feat.shape[0]
+    if grads is None:
+        grads = torch.empty_like(params)
+    if work is None:
+        work = torch.empty(2 * n * 128, dtype=torch.float32, device=feat.device)
+    _gcheck(lib().efe_mlp_backward(_stream(stream), _ptr(params), _ptr(feat), _ptr(acts),
+                                   _ptr(dout), n, _ptr(grads), _ptr(work)), "efe_mlp_backward")
+    return grads
+
+
+def efe_mlp_adam(params, grads, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _gcheck(lib().efe_mlp_adam(_stream(stream), _ptr(params), _ptr(grads), _ptr(m), _ptr(v),
+                               params.numel(), float(lr), float(beta1), float(beta2), float(eps),
+                               int(step)), "efe_mlp_adam")
 
 
 # module-level names of the C entry points
