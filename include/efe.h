@@ -155,10 +155,13 @@ efe_status efe_cheb_filter(efe_ctx *ctx, double *V, const double *lambda, int32_
                            int64_t ld, const efe_cheb_params *prm);
 
 /* Rayleigh-Ritz in FP64 (Eq. projectedKSEig): S = V^T M V, Hp = V^T H V,
- * S = L L^T, L^-1 Hp L^-T = Q Lambda Q^T (Jacobi), V <- V L^-T Q.
+ * Hp R = S R Lambda with R^T S R = I (dense generalized eigensolve on the
+ * GPU: Cholesky of S, reduction, divide and conquer), V <- V R.
  * lambda (device, ncols) ascending; resnorm (device, ncols, may be NULL)
  * = ||H v_j - lambda_j M v_j||_2.  Boundary rows of V are set to zero.
- * Returns EFE_ENUMERIC if S is not positive definite. */
+ * Any block width: H V is formed in column chunks, the rotation in row
+ * blocks in place.  Returns EFE_ENUMERIC if S is not positive definite or
+ * the dense eigensolve does not converge. */
 efe_status efe_rayleigh_ritz(efe_ctx *ctx, double *V, int32_t ncols, int64_t ld,
                              double *lambda, double *resnorm);
 

@@ -61,6 +61,18 @@ def occupations(eps, mu, kT):
     return expit(-(np.asarray(eps) - mu) / kT)
 
 
+def electron_excess(eps, mu, n_electrons, kT):
+    """2 sum_i f(eps_i, mu) - N_e written as the integer 2 #{eps_i <= mu} - N_e
+    plus the Fermi tails 2 (sum_{eps_i > mu} f_i - sum_{eps_i <= mu} (1 - f_i)),
+    each tail term formed without cancellation (1 - f(x) = expit(x) for
+    x = (eps - mu)/kT <= 0).  Inside a gap much wider than kT the plain sum is
+    flat to rounding; this form keeps its sign resolved there."""
+    x = (np.asarray(eps, float) - mu) / kT
+    below = x <= 0.0
+    tails = np.sum(expit(-x[~below])) - np.sum(expit(x[below]))
+    return (2.0 * np.count_nonzero(below) - n_electrons) + 2.0 * tails
+
+
 def fermi_level(eps, n_electrons, kT, iters=200):
     """mu with 2 sum_i f(eps_i, mu) = N_e by bisection (Eq. electronconstraint)."""
     eps = np.asarray(eps, float)
@@ -68,7 +80,7 @@ def fermi_level(eps, n_electrons, kT, iters=200):
     hi = eps.max() + 50.0 * kT + 1.0
     for _ in range(iters):
         mu = 0.5 * (lo + hi)
-        if 2.0 * occupations(eps, mu, kT).sum() < n_electrons:
+        if electron_excess(eps, mu, n_electrons, kT) < 0.0:
             lo = mu
         else:
             hi = mu

@@ -14,39 +14,82 @@
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
+// columns per lane (x 64) of the row-reduction kernels
+constexpr int POST_Q = 3;
+
 // ------------------------------------------------------------------ pre
+// One wave per group of 8 consecutive nodes, one lane per column (up to 192
+// columns per pass, three per lane).  For every atom of the group's union
+// the nine X^E rows are read once and applied to all eight nodes with the
+// group-major coefficients (uniform over the wave, so they come through the
+// scalar cache): Xh = s X^C - C^T X^E and Y^C = B^T X^E.
+constexpr int PRE_Q = 3;
 __global__ __launch_bounds__(256) void k_pre(int64_t n_nodes, int ncols, const double *__restrict__ XC,
                                              int64_t ldx, const double *__restrict__ scale,
                                              const double *__restrict__ minv,
                                              const double *__restrict__ XE, int64_t lde,
-                                             const int32_t *__restrict__ nm_ptr,
-                                             const int32_t *__restrict__ nm_atom,
-                                             const double *__restrict__ C_nm,
-                                             const double *__restrict__ B_nm, int nf,
+                                             const int32_t *__restrict__ g_ptr,
+                                             const int32_t *__restrict__ g_atom,
+                                             const double *__restrict__ Cg,
+                                             const double *__restrict__ Bg, int nf,
                                              double *__restrict__ Xh, int64_t ldh,
                                              double *Y, int64_t ldy) {
-  const int64_t j = (int64_t)blockIdx.x * 4 + threadIdx.y;
-  if (j >= n_nodes) return;
-  const bool inner = minv[j] != 0.0;
-  const double s = scale ? scale[j] : 1.0;
-  const int32_t e0 = nm_ptr[j], e1 = nm_ptr[j + 1];
-  for (int col = threadIdx.x; col < ncols; col += 64) {
-    double xh = 0.0, y = 0.0;
-    if (inner) {
-      xh = s * XC[j * ldx + col];
-      for (int32_t e = e0; e < e1; ++e) {
-        const double *xe = XE + (int64_t)nm_atom[e] * nf * lde + col;
-        const double *cc = C_nm + (int64_t)e * nf;
-        const double *bb = B_nm + (int64_t)e * nf;
-        for (int k = 0; k < nf; ++k) {
-          const double v = xe[(int64_t)k * lde];
-          xh -= cc[k] * v;
-          if (Y) y += bb[k] * v;
+  const int64_t grp = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + threadIdx.x / 64));
+  const int lane = threadIdx.x % 64;
+  const int64_t n0 = grp * 8;
+  if (n0 >= n_nodes) return;
+  const int nn = (int)min<int64_t>(8, n_nodes - n0);
+  double s[8];
+  bool inner[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    inner[j] = j < nn && minv[n0 + j] != 0.0;
+    s[j] = j < nn ? (scale ? scale[n0 + j] : 1.0) : 0.0;
+  }
+  const int32_t a0 = g_ptr[grp], a1 = g_ptr[grp + 1];
+  for (int c0 = 0; c0 < ncols; c0 += 64 * PRE_Q) {
+    double xh[PRE_Q][8], y[PRE_Q][8];
+#pragma unroll
+    for (int q = 0; q < PRE_Q; ++q) {
+      const int col = c0 + 64 * q + lane;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        xh[q][j] = (inner[j] && col < ncols) ? s[j] * XC[(n0 + j) * ldx + col] : 0.0;
+        y[q][j] = 0.0;
+      }
+    }
+    for (int32_t a = a0; a < a1; ++a) {
+      const double *xe = XE + (int64_t)g_atom[a] * nf * lde;
+      const double *cg = Cg + (int64_t)a * nf * 8, *bg = Bg + (int64_t)a * nf * 8;
+      for (int k = 0; k < nf; ++k) {
+        double v[PRE_Q];
+#pragma unroll
+        for (int q = 0; q < PRE_Q; ++q) {
+          const int col = c0 + 64 * q + lane;
+          v[q] = col < ncols ? xe[(int64_t)k * lde + col] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const double cj = cg[k * 8 + j], bj = bg[k * 8 + j];
+#pragma unroll
+          for (int q = 0; q < PRE_Q; ++q) {
+            xh[q][j] -= cj * v[q];
+            y[q][j] += bj * v[q];
+          }
         }
       }
     }
-    Xh[j * ldh + col] = xh;
-    if (Y) Y[j * ldy + col] = y;
+#pragma unroll
+    for (int q = 0; q < PRE_Q; ++q) {
+      const int col = c0 + 64 * q + lane;
+      if (col >= ncols) continue;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        if (j >= nn) continue;
+        Xh[(n0 + j) * ldh + col] = inner[j] ? xh[q][j] : 0.0;
+        if (Y) Y[(n0 + j) * ldy + col] = inner[j] ? y[q][j] : 0.0;
+      }
+    }
   }
 }
 
@@ -97,6 +140,7 @@ __global__ __launch_bounds__(256) void k_cell2(int ncells, int nparts,
   typedef typename M::acc_t acc_t;
   constexpr int CBM = CELL_CBM, NC = CBM * 16, KC = 16, EPT = KC * NC / 256;
   __shared__ T Xs[2][KC][M::NCP];
+  __shared__ int32_t gs[EFE_MAXLOC];   // the cell's node numbers
   const int b = blockIdx.x;
   const int xcd = b % 8, slot = b / 8;
   const int ci = (slot / nparts) * 8 + xcd;
@@ -105,12 +149,13 @@ __global__ __launch_bounds__(256) void k_cell2(int ncells, int nparts,
   const int cell = cells[ci];
   const int32_t *g = c2g + (int64_t)cell * nloc;
   const int t = threadIdx.x, wave = t / 64, lane = t % 64, li = lane % 16, lk = lane / 16;
+  for (int l = t; l < nloc; l += 256) gs[l] = g[l];
+  __syncthreads();
   const int rbase = (part * 4 + wave) * RBW;
   const int CB = (ncols + 15) / 16;
   const int NCH = (KS + 3) / 4;
   const T *hp = Ht + ((int64_t)cell * RB) * KS * 64 + lane;
 
-  T xr[EPT];
   T a0[4][RBW], a1[4][RBW];
   acc_t acc[RBW][CBM];
 #pragma unroll
@@ -118,41 +163,46 @@ __global__ __launch_bounds__(256) void k_cell2(int ncells, int nparts,
 #pragma unroll
     for (int cb = 0; cb < CBM; ++cb) acc[r][cb] = (acc_t){0, 0, 0, 0};
 
+  // Loads are unconditional, at clamped addresses, and nothing consumes a
+  // loaded value before it is needed, so the compiler waits only for the
+  // current chunk's operands and the next chunk's loads stay in flight.
+  // Out-of-range X rows and columns are zeroed when they are written to LDS;
+  // a clamped A fragment then multiplies zero rows of Xs (k past the end) or
+  // feeds accumulators that are never stored (row blocks past the end).
+  double xr[EPT];
   auto stage_load = [&](int ch) {
 #pragma unroll
     for (int j = 0; j < EPT; ++j) {
       const int idx = t + 256 * j, r = idx / NC, cc = idx % NC, k = ch * KC + r;
-      xr[j] = (k < nloc && cc < ncols) ? (T)Xh[(int64_t)g[k] * ldx + cc] : (T)0;
+      xr[j] = Xh[(int64_t)gs[min(k, nloc - 1)] * ldx + min(cc, ncols - 1)];
     }
   };
-  auto stage_store = [&](int buf) {
+  auto stage_store = [&](int buf, int ch) {
 #pragma unroll
     for (int j = 0; j < EPT; ++j) {
-      const int idx = t + 256 * j;
-      Xs[buf][idx / NC][idx % NC] = xr[j];
+      const int idx = t + 256 * j, r = idx / NC, cc = idx % NC, k = ch * KC + r;
+      Xs[buf][r][cc] = (k < nloc && cc < ncols) ? (T)xr[j] : (T)0;
     }
   };
   auto a_load = [&](int ch, T (&dst)[4][RBW]) {
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
-      for (int r = 0; r < RBW; ++r) {
-        const int ks = ch * 4 + s, rb = rbase + r;
-        dst[s][r] = (ks < KS && rb < RB) ? hp[((int64_t)rb * KS + ks) * 64] : (T)0;
-      }
+      for (int r = 0; r < RBW; ++r)
+        dst[s][r] = hp[((int64_t)min(rbase + r, RB - 1) * KS + min(ch * 4 + s, KS - 1)) * 64];
   };
-  auto compute = [&](int buf, const T (&src)[4][RBW], int ch) {
+  // k steps past the end meet zero rows of Xs and zero A fragments, and
+  // column blocks past the end zero columns: all MFMAs run unconditionally
+  auto compute = [&](int buf, const T (&src)[4][RBW]) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      if (ch * 4 + s >= KS) break;
       T bv[CBM];
 #pragma unroll
       for (int cb = 0; cb < CBM; ++cb) bv[cb] = Xs[buf][s * 4 + lk][cb * 16 + li];
 #pragma unroll
       for (int r = 0; r < RBW; ++r)
 #pragma unroll
-        for (int cb = 0; cb < CBM; ++cb)
-          if (cb < CB) acc[r][cb] = M::op(src[s][r], bv[cb], acc[r][cb]);
+        for (int cb = 0; cb < CBM; ++cb) acc[r][cb] = M::op(src[s][r], bv[cb], acc[r][cb]);
     }
   };
   auto step = [&](int ch, const T (&cur)[4][RBW], T (&nxt)[4][RBW], int buf) {
@@ -161,35 +211,48 @@ __global__ __launch_bounds__(256) void k_cell2(int ncells, int nparts,
       stage_load(ch + 1);
       a_load(ch + 1, nxt);
     }
-    compute(buf, cur, ch);
-    if (more) stage_store(buf ^ 1);
+    compute(buf, cur);
+    if (more) stage_store(buf ^ 1, ch + 1);
     __syncthreads();
   };
 
   stage_load(0);
   a_load(0, a0);
-  stage_store(0);
+  stage_store(0, 0);
   __syncthreads();
   for (int ch = 0; ch < NCH; ch += 2) {
     step(ch, a0, a1, 0);
     if (ch + 1 < NCH) step(ch + 1, a1, a0, 1);
   }
+  // scatter: per row block, all reads of Y first, then all writes, so the
+  // reads overlap instead of each waiting for the one before
 #pragma unroll
   for (int r = 0; r < RBW; ++r) {
     const int rb = rbase + r;
     if (rb >= RB) continue;
+    int64_t node[4];
+    bool ok[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int row = rb * 16 + M::row(v, lk);
-      if (row >= nloc) continue;
-      const int64_t node = g[row];
-      if (minv[node] == 0.0) continue;
+      node[v] = gs[min(row, nloc - 1)];
+      ok[v] = row < nloc;
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) ok[v] = ok[v] && minv[node[v]] != 0.0;
+    double yv[4][CBM];
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int cb = 0; cb < CBM; ++cb)
+        yv[v][cb] = Y[node[v] * ldy + min(cb * 16 + li, ncols - 1)];
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
 #pragma unroll
       for (int cb = 0; cb < CBM; ++cb) {
         const int col = cb * 16 + li;
-        if (cb < CB && col < ncols) Y[node * ldy + col] += (double)acc[r][cb][v];
+        if (ok[v] && cb < CB && col < ncols) Y[node[v] * ldy + col] = yv[v][cb] + (double)acc[r][cb][v];
       }
-    }
   }
 }
 
@@ -257,79 +320,154 @@ __global__ __launch_bounds__(256) void k_cell_bf16(int ncells, int ntiles,
 }
 
 // ------------------------------------------------------------------ projectors
-__global__ __launch_bounds__(256) void k_kb_project(int ncols, const int32_t *__restrict__ kbnode_ptr,
+// W[I] += D_I sum_s P^C_s Xh[node_s] over one work item (atom, support-list
+// range); the items of a node region run back to back, so the rows of Xh
+// they read are shared through the caches.  Waves take one support node at a
+// time (wave-uniform) for up to 192 columns, three per lane.
+__global__ __launch_bounds__(256) void k_kb_project(int ncols, const int32_t *__restrict__ items,
                                                     const int32_t *__restrict__ kbnode,
                                                     const double *__restrict__ Pc,
                                                     const double *__restrict__ Xh, int64_t ldh,
-                                                    const double *__restrict__ Pphi, int64_t n_enr,
-                                                    const double *__restrict__ XE, int64_t lde,
                                                     const double *__restrict__ D,
                                                     double *__restrict__ W) {
-  __shared__ double red[4][64];
-  const int I = blockIdx.x;
-  const int col = blockIdx.y * 64 + threadIdx.x;
-  double acc = 0.0;
-  if (col < ncols) {
-    for (int32_t s = kbnode_ptr[I] + threadIdx.y; s < kbnode_ptr[I + 1]; s += 4)
-      acc += Pc[s] * Xh[(int64_t)kbnode[s] * ldh + col];
-    for (int64_t f = threadIdx.y; f < n_enr; f += 4)
-      acc += Pphi[(int64_t)I * n_enr + f] * XE[f * lde + col];
+  __shared__ double red[3][64 * POST_Q];
+  const int32_t *it = items + 3 * (int64_t)blockIdx.x;
+  const int I = it[0];
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
+  const int lane = threadIdx.x % 64;
+  const int c0 = blockIdx.y * 64 * POST_Q;
+  double acc[POST_Q] = {0.0, 0.0, 0.0};
+  for (int32_t s = it[1] + wave; s < it[2]; s += 4) {
+    const int64_t node = kbnode[s];
+    const double p = Pc[s];
+#pragma unroll
+    for (int q = 0; q < POST_Q; ++q) {
+      const int col = c0 + 64 * q + lane;
+      if (col < ncols) acc[q] += p * Xh[node * ldh + col];
+    }
   }
-  red[threadIdx.y][threadIdx.x] = acc;
+  if (wave > 0)
+#pragma unroll
+    for (int q = 0; q < POST_Q; ++q) red[wave - 1][64 * q + lane] = acc[q];
   __syncthreads();
-  if (threadIdx.y == 0 && col < ncols)
-    W[(int64_t)I * ncols + col] =
-        D[I] * (red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x]);
+  if (wave == 0)
+#pragma unroll
+    for (int q = 0; q < POST_Q; ++q) {
+      const int col = c0 + 64 * q + lane;
+      if (col < ncols)
+        atomicAdd(&W[(int64_t)I * ncols + col],
+                  D[I] * (acc[q] + red[0][64 * q + lane] + red[1][64 * q + lane] +
+                          red[2][64 * q + lane]));
+    }
 }
 
+// W[I] = D_I sum_f P^phi_If XE_f (first term of the projector coefficients)
+__global__ __launch_bounds__(256) void k_kb_w_pphi(int nproj, int ncols, int64_t n_enr,
+                                                 const double *__restrict__ Pphi,
+                                                 const double *__restrict__ XE, int64_t lde,
+                                                 const double *__restrict__ D,
+                                                 double *__restrict__ W) {
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)nproj * ncols) return;
+  const int I = (int)(idx / ncols), col = (int)(idx % ncols);
+  double acc = 0.0;
+  for (int64_t f = 0; f < n_enr; ++f) acc += Pphi[(int64_t)I * n_enr + f] * XE[f * lde + col];
+  W[idx] = D[I] * acc;
+}
+
+// Y^C[node] += sum_e P^C_e W[atom_e] over the node's projector entries; one
+// wave per node (wave-uniform entry list), three columns per lane.
 __global__ __launch_bounds__(256) void k_kb_expand(int64_t n_nodes, int ncols,
                                                    const int32_t *__restrict__ kbnm_ptr,
                                                    const int32_t *__restrict__ kbnm_atom,
                                                    const double *__restrict__ Pc_nm,
                                                    const double *__restrict__ W,
                                                    double *__restrict__ Y, int64_t ldy) {
-  const int64_t j = (int64_t)blockIdx.x * 4 + threadIdx.y;
+  const int64_t j = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
   if (j >= n_nodes) return;
+  const int lane = threadIdx.x % 64;
   const int32_t e0 = kbnm_ptr[j], e1 = kbnm_ptr[j + 1];
   if (e0 == e1) return;
-  for (int col = threadIdx.x; col < ncols; col += 64) {
-    double acc = 0.0;
-    for (int32_t e = e0; e < e1; ++e) acc += Pc_nm[e] * W[(int64_t)kbnm_atom[e] * ncols + col];
-    Y[j * ldy + col] += acc;
+  for (int c0 = 0; c0 < ncols; c0 += 64 * POST_Q) {
+    double acc[POST_Q] = {0.0, 0.0, 0.0};
+    for (int32_t e = e0; e < e1; ++e) {
+      const double p = Pc_nm[e];
+      const double *w = W + (int64_t)kbnm_atom[e] * ncols;
+#pragma unroll
+      for (int q = 0; q < POST_Q; ++q) {
+        const int col = c0 + 64 * q + lane;
+        if (col < ncols) acc[q] += p * w[col];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < POST_Q; ++q) {
+      const int col = c0 + 64 * q + lane;
+      if (col < ncols) Y[j * ldy + col] += acc[q];
+    }
   }
 }
 
-// Y^E[I k] += sum over the atom's support nodes of B[s][k] Xh[node] - C[s][k] Y[node]
-__global__ __launch_bounds__(256) void k_enr_post(int nf, int ncols, int chunk,
-                                                  const int32_t *__restrict__ snode_ptr,
+// Y^E[I] += sum_s (B_s Xh[node_s] - C_s Y[node_s]) over one work item
+// (atom I, range of its support list).  Each wave takes one support node at a
+// time (wave-uniform, so the 2 x nf coefficients come through the scalar
+// cache) for up to 192 columns, three per lane; the four waves' sums meet in
+// LDS and are added to Y^E once per item.
+__global__ __launch_bounds__(256) void k_enr_post(int nf, int ncols,
+                                                  const int32_t *__restrict__ items,
                                                   const int32_t *__restrict__ snode,
                                                   const double *__restrict__ B_am,
                                                   const double *__restrict__ C_am,
                                                   const double *__restrict__ Xh, int64_t ldh,
                                                   const double *__restrict__ Y, int64_t ldy,
                                                   double *__restrict__ YE, int64_t lde) {
-  __shared__ double red[4][9][64];
-  const int I = blockIdx.x;
-  const int32_t s0 = snode_ptr[I] + blockIdx.y * chunk;
-  const int32_t s1 = min(snode_ptr[I + 1], s0 + chunk);
-  if (s0 >= s1) return;
-  const int col = blockIdx.z * 64 + threadIdx.x;
-  double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-  if (col < ncols) {
-    for (int32_t s = s0 + threadIdx.y; s < s1; s += 4) {
-      const int64_t node = snode[s];
-      const double xh = Xh[node * ldh + col], y = Y[node * ldy + col];
-      const double *bb = B_am + (int64_t)s * nf, *cc = C_am + (int64_t)s * nf;
-      for (int k = 0; k < nf; ++k) acc[k] += bb[k] * xh - cc[k] * y;
+  __shared__ double red[3][9][64 * POST_Q];
+  const int32_t *it = items + 3 * (int64_t)blockIdx.x;
+  const int I = it[0];
+  const int32_t s0 = it[1], s1 = it[2];
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
+  const int lane = threadIdx.x % 64;
+  const int c0 = blockIdx.y * 64 * POST_Q;
+  double acc[POST_Q][9];
+#pragma unroll
+  for (int q = 0; q < POST_Q; ++q)
+#pragma unroll
+    for (int k = 0; k < 9; ++k) acc[q][k] = 0.0;
+  for (int32_t s = s0 + wave; s < s1; s += 4) {
+    const int64_t node = snode[s];
+    const double *bb = B_am + (int64_t)s * nf, *cc = C_am + (int64_t)s * nf;
+    double xh[POST_Q], y[POST_Q];
+#pragma unroll
+    for (int q = 0; q < POST_Q; ++q) {
+      const int col = c0 + 64 * q + lane;
+      xh[q] = col < ncols ? Xh[node * ldh + col] : 0.0;
+      y[q] = col < ncols ? Y[node * ldy + col] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const double b = k < nf ? bb[k] : 0.0, c = k < nf ? cc[k] : 0.0;
+#pragma unroll
+      for (int q = 0; q < POST_Q; ++q) acc[q][k] += b * xh[q] - c * y[q];
     }
   }
-  for (int k = 0; k < nf; ++k) red[threadIdx.y][k][threadIdx.x] = acc[k];
+  if (wave > 0)
+#pragma unroll
+    for (int q = 0; q < POST_Q; ++q)
+#pragma unroll
+      for (int k = 0; k < 9; ++k) red[wave - 1][k][64 * q + lane] = acc[q][k];
   __syncthreads();
-  if (threadIdx.y == 0 && col < ncols)
-    for (int k = 0; k < nf; ++k)
-      atomicAdd(&YE[(int64_t)(I * nf + k) * lde + col],
-                red[0][k][threadIdx.x] + red[1][k][threadIdx.x] + red[2][k][threadIdx.x] +
-                    red[3][k][threadIdx.x]);
+  if (wave == 0) {
+#pragma unroll
+    for (int q = 0; q < POST_Q; ++q) {
+      const int col = c0 + 64 * q + lane;
+      if (col >= ncols) continue;
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        const double v = acc[q][k] + red[0][k][64 * q + lane] + red[1][k][64 * q + lane] +
+                         red[2][k][64 * q + lane];
+        if (k < nf) atomicAdd(&YE[(int64_t)(I * nf + k) * lde + col], v);
+      }
+    }
+  }
 }
 
 // ------------------------------------------------------------------ overlap
@@ -396,18 +534,21 @@ efe_status efe_apply_H_internal(efe_ctx *c, const double *XC, int64_t ldx, const
   const int t_apply = efe_timer_begin(c, EFE_T_APPLY);
   // pre: Xh and Y^C = B^T X^E
   {
-    dim3 blk(64, 4);
     const int t = efe_timer_begin(c, EFE_T_PRE);
-    k_pre<<<cdiv(c->n_nodes, 4), blk, 0, c->stream>>>(
-        c->n_nodes, ncols, XC, ldx, scale, c->d_minv, XE, lde, c->d_nm_ptr, c->d_nm_atom, c->d_C_nm,
-        c->d_B_nm, nf, Xh, ldh, Y, ldy);
+    k_pre<<<cdiv(c->n_nodes, 32), 256, 0, c->stream>>>(c->n_nodes, ncols, XC, ldx, scale,
+                                                       c->d_minv, XE, lde, c->d_g_ptr, c->d_g_atom,
+                                                       c->d_Cg, c->d_Bg, nf, Xh, ldh, Y, ldy);
     efe_timer_end(c, EFE_T_PRE, t);
   }
   // projector coefficients
   if (c->nproj) {
-    dim3 blk(64, 4), grd(c->nproj, cdiv(ncols, 64));
-    k_kb_project<<<grd, blk, 0, c->stream>>>(ncols, c->d_kbnode_ptr, c->d_kbnode, c->d_Pc_am, Xh,
-                                             ldh, c->d_Pphi, c->n_enr, XE, lde, c->d_D, W);
+    k_kb_w_pphi<<<cdiv((int64_t)c->nproj * ncols, 256), 256, 0, c->stream>>>(
+        c->nproj, ncols, c->n_enr, c->d_Pphi, XE, lde, c->d_D, W);
+    if (c->n_kb_items) {
+      dim3 grd(c->n_kb_items, cdiv(ncols, 64 * POST_Q));
+      k_kb_project<<<grd, 256, 0, c->stream>>>(ncols, c->d_kb_items, c->d_kbnode, c->d_Pc_am, Xh,
+                                               ldh, c->d_D, W);
+    }
   }
   // cell GEMM, colour by colour
   if (prec == EFE_FP64) {
@@ -430,8 +571,7 @@ efe_status efe_apply_H_internal(efe_ctx *c, const double *XC, int64_t ldx, const
     }
   }
   if (c->nproj) {
-    dim3 blk(64, 4);
-    k_kb_expand<<<cdiv(c->n_nodes, 4), blk, 0, c->stream>>>(c->n_nodes, ncols, c->d_kbnm_ptr,
+    k_kb_expand<<<cdiv(c->n_nodes, 4), 256, 0, c->stream>>>(c->n_nodes, ncols, c->d_kbnm_ptr,
                                                             c->d_kbnm_atom, c->d_Pc_nm, W, Y, ldy);
   }
   // enrichment rows
@@ -444,13 +584,11 @@ efe_status efe_apply_H_internal(efe_ctx *c, const double *XC, int64_t ldx, const
         (s = efe_gemm(c, true, false, c->n_enr, ncols, c->nproj, 1.0, c->d_Pphi, c->n_enr, W, ncols,
                       1.0, YE, ldy)))
       return s;
-    int maxs = 0;
-    for (int I = 0; I < c->natoms; ++I)
-      maxs = std::max(maxs, c->snode_ptr_h[I + 1] - c->snode_ptr_h[I]);
-    const int chunk = 1024;
-    dim3 blk(64, 4), grd(c->natoms, cdiv(maxs, chunk), cdiv(ncols, 64));
-    k_enr_post<<<grd, blk, 0, c->stream>>>(nf, ncols, chunk, c->d_snode_ptr, c->d_snode,
-                                           c->d_B_am, c->d_C_am, Xh, ldh, Y, ldy, YE, ldy);
+    if (c->n_enr_items) {
+      dim3 grd(c->n_enr_items, cdiv(ncols, 64 * POST_Q));
+      k_enr_post<<<grd, 256, 0, c->stream>>>(nf, ncols, c->d_enr_items, c->d_snode, c->d_B_am,
+                                             c->d_C_am, Xh, ldh, Y, ldy, YE, ldy);
+    }
   }
   efe_timer_end(c, EFE_T_POST, t_post);
   efe_timer_end(c, EFE_T_APPLY, t_apply);
@@ -461,10 +599,10 @@ efe_status efe_apply_H_internal(efe_ctx *c, const double *XC, int64_t ldx, const
 efe_status efe_transform_cfe(efe_ctx *c, const double *X, int64_t ldx, double *Xh, int64_t ldh,
                              int ncols) {
   if (ncols <= 0) return EFE_OK;
-  dim3 blk(64, 4);
-  k_pre<<<cdiv(c->n_nodes, 4), blk, 0, c->stream>>>(
-      c->n_nodes, ncols, X, ldx, nullptr, c->d_minv, X + c->n_nodes * ldx, ldx, c->d_nm_ptr,
-      c->d_nm_atom, c->d_C_nm, c->d_B_nm, c->nf, Xh, ldh, nullptr, 0);
+  k_pre<<<cdiv(c->n_nodes, 32), 256, 0, c->stream>>>(c->n_nodes, ncols, X, ldx, nullptr, c->d_minv,
+                                                     X + c->n_nodes * ldx, ldx, c->d_g_ptr,
+                                                     c->d_g_atom, c->d_Cg, c->d_Bg, c->nf, Xh, ldh,
+                                                     nullptr, 0);
   HIPCHK(c, hipGetLastError());
   return EFE_OK;
 }

@@ -178,6 +178,34 @@ static void build_support(const efe_ctx *c, double rc, SupportTables &T) {
     }
 }
 
+// Work items of the atom-major reductions over support nodes: every atom's
+// (node-sorted) support list cut at multiples of `region` node indices and
+// at `maxlen` entries, as (atom, first, end) triples ordered by region, so
+// that consecutive work-groups read the same rows for different atoms.
+static void build_items(int natoms, const std::vector<int32_t> &ptr,
+                        const std::vector<int32_t> &snode, int32_t region, int32_t maxlen,
+                        std::vector<int32_t> &items) {
+  struct It { int32_t reg, atom, s0, s1; };
+  std::vector<It> v;
+  for (int I = 0; I < natoms; ++I) {
+    int32_t s = ptr[I];
+    while (s < ptr[I + 1]) {
+      const int32_t reg = snode[s] / region;
+      int32_t e = s + 1;
+      while (e < ptr[I + 1] && e - s < maxlen && snode[e] / region == reg) ++e;
+      v.push_back({reg, I, s, e});
+      s = e;
+    }
+  }
+  std::stable_sort(v.begin(), v.end(), [](const It &a, const It &b) { return a.reg < b.reg; });
+  items.clear();
+  for (const It &x : v) {
+    items.push_back(x.atom);
+    items.push_back(x.s0);
+    items.push_back(x.s1);
+  }
+}
+
 // (cell, I, J) for every cell and every pair of atoms from lists A and B whose
 // supports contain the cell.
 static void build_triples(const efe_ctx *c, const SupportTables &A, const SupportTables &B,
@@ -297,6 +325,34 @@ extern "C" efe_status efe_setup_mesh(const efe_mesh_desc *mesh, const efe_system
     TRY(upload(c, &c->d_nm_ptr, E.nm_ptr));
     TRY(upload(c, &c->d_nm_atom, E.nm_atom));
     TRY(upload(c, &c->d_nm_src, E.nm_src));
+    // groups of 8 consecutive nodes: union of their atoms, and per node-major
+    // entry the slot of its atom in its group's union
+    {
+      const int64_t G = cdiv(c->n_nodes, 8);
+      std::vector<int32_t> gptr(G + 1, 0), gatom, gslot(E.nm_atom.size());
+      std::vector<int32_t> u;
+      for (int64_t gi = 0; gi < G; ++gi) {
+        const int64_t n0 = gi * 8, n1 = std::min<int64_t>(n0 + 8, c->n_nodes);
+        u.assign(E.nm_atom.begin() + E.nm_ptr[n0], E.nm_atom.begin() + E.nm_ptr[n1]);
+        std::sort(u.begin(), u.end());
+        u.erase(std::unique(u.begin(), u.end()), u.end());
+        for (int64_t n = n0; n < n1; ++n)
+          for (int32_t e = E.nm_ptr[n]; e < E.nm_ptr[n + 1]; ++e)
+            gslot[e] = (int32_t)gatom.size() +
+                       (int32_t)(std::lower_bound(u.begin(), u.end(), E.nm_atom[e]) - u.begin());
+        gatom.insert(gatom.end(), u.begin(), u.end());
+        gptr[gi + 1] = (int32_t)gatom.size();
+      }
+      c->n_gslots = (int64_t)gatom.size();
+      TRY(upload(c, &c->d_g_ptr, gptr));
+      TRY(upload(c, &c->d_g_atom, gatom));
+      TRY(upload(c, &c->d_nm_gslot, gslot));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    std::vector<int32_t> items;
+    build_items(c->natoms, E.snode_ptr, E.snode, 4096, 1024, items);
+    c->n_enr_items = (int64_t)items.size() / 3;
+    TRY(upload(c, &c->d_enr_items, items));
     std::vector<int32_t> trip;
     if (c->nf > 0) build_triples(c, E, E, trip);
     c->ntrip = (int64_t)trip.size() / 3;
@@ -313,6 +369,10 @@ extern "C" efe_status efe_setup_mesh(const efe_mesh_desc *mesh, const efe_system
     TRY(upload(c, &c->d_kbnm_ptr, K.nm_ptr));
     TRY(upload(c, &c->d_kbnm_atom, K.nm_atom));
     TRY(upload(c, &c->d_kbnm_src, K.nm_src));
+    std::vector<int32_t> kbitems;
+    build_items(c->natoms, K.snode_ptr, K.snode, 4096, 1024, kbitems);
+    c->n_kb_items = (int64_t)kbitems.size() / 3;
+    TRY(upload(c, &c->d_kb_items, kbitems));
     std::vector<int32_t> kbtrip;
     if (c->nproj > 0 && c->nf > 0) build_triples(c, K, E, kbtrip);
     c->nkbtrip = (int64_t)kbtrip.size() / 3;
@@ -372,19 +432,21 @@ extern "C" void efe_destroy(efe_ctx *c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
   efe_scf_free(c);
+  efe_blas_destroy(c);
   void *ptrs[] = {c->d_c2g,       c->d_colour_order, c->d_m,          c->d_minv, c->d_m_int,
                   c->d_N3,        c->d_G3,           c->d_W3,         c->d_K,
                   c->d_xq1,       c->d_xyz,          c->d_Zs,         c->d_pair_atom,
                   c->d_pair_cell, c->d_pair_lmap,    c->d_snode_ptr,  c->d_snode,
                   c->d_nu,        c->d_b_am,         c->d_C_am,       c->d_Bkin_am,
                   c->d_B_am,      c->d_nm_ptr,       c->d_nm_atom,    c->d_nm_src,
-                  c->d_C_nm,      c->d_B_nm,         c->d_trip,       c->d_Mpp,
+                  c->d_trip,      c->d_Mpp,
                   c->d_Mee,       c->d_Hpp_kin,      c->d_Hpp,        c->d_Mee_inv,
                   c->d_kbpair_atom, c->d_kbpair_cell, c->d_kbpair_lmap, c->d_kbnode_ptr,
                   c->d_kbnode,    c->d_Pc_am,        c->d_kbnm_ptr,   c->d_kbnm_atom,
                   c->d_kbnm_src,  c->d_Pc_nm,        c->d_kbtrip,     c->d_Pphi,
                   c->d_D,         c->d_vq,           c->d_Htile64,    c->d_Htile32,
-                  c->d_Htile16};
+                  c->d_Htile16,   c->d_enr_items,    c->d_kb_items,   c->d_g_ptr,
+                  c->d_g_atom,    c->d_nm_gslot,     c->d_Cg,         c->d_Bg};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (auto &b : c->ws)

@@ -64,12 +64,19 @@ struct efe_ctx {
   // node-major copy: per node the list of (atom, support-node index)
   int64_t nnz_nm = 0;
   int32_t *d_nm_ptr = nullptr, *d_nm_atom = nullptr, *d_nm_src = nullptr;
-  double *d_C_nm = nullptr, *d_B_nm = nullptr;
+  // groups of 8 consecutive nodes: per group the union of the atoms whose
+  // support holds one of its nodes (slots), and C, B per slot as [slot][k][8]
+  int64_t n_gslots = 0;
+  int32_t *d_g_ptr = nullptr, *d_g_atom = nullptr, *d_nm_gslot = nullptr;
+  double *d_Cg = nullptr, *d_Bg = nullptr;
   // (cell, I, J) triples of atoms sharing a support cell
   int64_t ntrip = 0;
   int32_t *d_trip = nullptr;
   double *d_Mpp = nullptr, *d_Mee = nullptr, *d_Hpp_kin = nullptr, *d_Hpp = nullptr;
   double *d_Mee_inv = nullptr;                         // [natoms][nf][nf]
+  // (atom, first, end) work items over the support lists, ordered by node region
+  int64_t n_enr_items = 0, n_kb_items = 0;
+  int32_t *d_enr_items = nullptr, *d_kb_items = nullptr;
 
   // Kleinman-Bylander projectors (one per atom)
   int64_t nkbpairs = 0;
@@ -99,6 +106,8 @@ struct efe_ctx {
 
   // SCF state (scf.hip)
   void *scf = nullptr;
+  // rocBLAS handle of the dense eigensolver (created on first use)
+  void *blas = nullptr;
 
   // event timing (efe_timing)
   bool timing = false;
@@ -123,12 +132,20 @@ struct efe_ctx {
   } while (0)
 
 efe_status efe_alloc(efe_ctx *ctx, void **p, size_t bytes);
+// rocBLAS handle bound to the context's stream (rr.hip)
+efe_status efe_blas_handle(efe_ctx *ctx, void **handle);
+void efe_blas_destroy(efe_ctx *ctx);
 // message returned by efe_last_error(NULL) (calls that take no context)
 void efe_set_global_error(const std::string &msg);
 // workspace slot `slot` of at least `bytes` bytes (kept across calls)
 efe_status efe_ws(efe_ctx *ctx, int slot, size_t bytes, void **p);
 
 static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Column chunk of the wide-block passes (filter, Rayleigh-Ritz H V, density):
+// the cell GEMM's column tile, and the width the per-pass workspaces are
+// sized for.
+constexpr int32_t EFE_COL_CHUNK = 160;
 
 // ------------------------------------------------------------------ launchers
 // setup / operators (setup.hip)

@@ -94,19 +94,10 @@ __global__ void k_copy_in(int64_t rows, int ncols, const double *__restrict__ sr
 }
 
 // ------------------------------------------------------------------ filter
-extern "C" efe_status efe_cheb_filter(efe_ctx *c, double *V, const double *lambda, int32_t ncols,
-                                      int64_t ld, const efe_cheb_params *prm) {
-  if (!c) return EFE_EINVAL;
-  if (!V || !prm || ncols < 0 || ld < ncols || ld < 1) EFE_FAIL(c, EFE_EINVAL, "bad arguments");
-  if (prm->degree < 1) EFE_FAIL(c, EFE_EINVAL, "degree must be >= 1");
-  if (!(prm->a < prm->b) || !(prm->a_min < prm->a)) EFE_FAIL(c, EFE_EINVAL, "need a_min < a < b");
-  if (prm->mode != EFE_FILTER_RESIDUAL && prm->mode != EFE_FILTER_STANDARD)
-    EFE_FAIL(c, EFE_EINVAL, "bad filter mode");
-  if (prm->prec != EFE_FP64 && prm->prec != EFE_FP32 && prm->prec != EFE_BF16)
-    EFE_FAIL(c, EFE_EINVAL, "bad filter precision");
-  if (prm->mode == EFE_FILTER_RESIDUAL && !lambda) EFE_FAIL(c, EFE_EINVAL, "residual mode needs lambda");
-  if (!c->have_potential) EFE_FAIL(c, EFE_ESTATE, "no potential set");
-  if (ncols == 0) return EFE_OK;
+// One column chunk of the filter (the filter acts on every column on its own,
+// so chunks of a wide block give the same result as one pass over it).
+static efe_status filter_chunk(efe_ctx *c, double *V, const double *lambda, int32_t ncols,
+                               int64_t ld, const efe_cheb_params *prm) {
   efe_status s;
   const int m = prm->degree;
   const double cc = 0.5 * (prm->a + prm->b), e = 0.5 * (prm->b - prm->a);
@@ -172,6 +163,26 @@ extern "C" efe_status efe_cheb_filter(efe_ctx *c, double *V, const double *lambd
   if ((s = efe_enr_block_inv(c, Zc + nn * ncols, ncols, XE, ncols, ncols))) return s;
   k_vout<<<nb, T, 0, c->stream>>>(nn, rows, ncols, c->d_minv, Zc, XE, Cl + (int64_t)m * ncols, V, ld);
   HIPCHK(c, hipGetLastError());
+  return EFE_OK;
+}
+
+extern "C" efe_status efe_cheb_filter(efe_ctx *c, double *V, const double *lambda, int32_t ncols,
+                                      int64_t ld, const efe_cheb_params *prm) {
+  if (!c) return EFE_EINVAL;
+  if (!V || !prm || ncols < 0 || ld < ncols || ld < 1) EFE_FAIL(c, EFE_EINVAL, "bad arguments");
+  if (prm->degree < 1) EFE_FAIL(c, EFE_EINVAL, "degree must be >= 1");
+  if (!(prm->a < prm->b) || !(prm->a_min < prm->a)) EFE_FAIL(c, EFE_EINVAL, "need a_min < a < b");
+  if (prm->mode != EFE_FILTER_RESIDUAL && prm->mode != EFE_FILTER_STANDARD)
+    EFE_FAIL(c, EFE_EINVAL, "bad filter mode");
+  if (prm->prec != EFE_FP64 && prm->prec != EFE_FP32 && prm->prec != EFE_BF16)
+    EFE_FAIL(c, EFE_EINVAL, "bad filter precision");
+  if (prm->mode == EFE_FILTER_RESIDUAL && !lambda) EFE_FAIL(c, EFE_EINVAL, "residual mode needs lambda");
+  if (!c->have_potential) EFE_FAIL(c, EFE_ESTATE, "no potential set");
+  efe_status s;
+  for (int32_t j0 = 0; j0 < ncols; j0 += EFE_COL_CHUNK) {
+    const int32_t nc = std::min<int32_t>(EFE_COL_CHUNK, ncols - j0);
+    if ((s = filter_chunk(c, V + j0, lambda ? lambda + j0 : nullptr, nc, ld, prm))) return s;
+  }
   return EFE_OK;
 }
 

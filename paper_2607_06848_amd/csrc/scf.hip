@@ -236,11 +236,24 @@ __global__ void k_fermi(int N, const double *__restrict__ lam, double ne, double
   }
   lo -= 50.0 * kT + 1.0;
   hi += 50.0 * kT + 1.0;
+  // 2 sum f - N_e as the integer 2 #{lam <= mu} - N_e plus the Fermi tails
+  // (f above mu, 1 - f below, each without cancellation), so that the sign
+  // stays resolved inside a gap much wider than kT
   for (int it = 0; it < 200; ++it) {
     const double mu = 0.5 * (lo + hi);
-    double s = 0.0;
-    for (int i = 0; i < N; ++i) s += 1.0 / (1.0 + exp((lam[i] - mu) / kT));
-    if (2.0 * s < ne) lo = mu;
+    double up = 0.0, down = 0.0;
+    int nbelow = 0;
+    for (int i = 0; i < N; ++i) {
+      const double x = (lam[i] - mu) / kT;
+      if (x <= 0.0) {
+        ++nbelow;
+        down += 1.0 / (1.0 + exp(-x));
+      } else {
+        up += 1.0 / (1.0 + exp(x));
+      }
+    }
+    const double excess = (2.0 * nbelow - ne) + 2.0 * (up - down);
+    if (excess < 0.0) lo = mu;
     else hi = mu;
   }
   const double mu = 0.5 * (lo + hi);
@@ -270,7 +283,7 @@ __global__ __launch_bounds__(256) void k_density(MeshGeo g, EnrParam e, const do
                                                  const int32_t *__restrict__ cell_atom,
                                                  const double *__restrict__ xyz,
                                                  const double *__restrict__ nu,
-                                                 double *__restrict__ rho) {
+                                                 double *__restrict__ rho, int accumulate) {
   __shared__ double xs[EFE_MAXLOC][16];
   __shared__ double ve[16][16 * 9];      // up to 16 atoms of the cell at a time
   const int64_t cell = blockIdx.x;
@@ -325,7 +338,7 @@ __global__ __launch_bounds__(256) void k_density(MeshGeo g, EnrParam e, const do
   }
   for (int r = 0; r < 2; ++r) {
     const int q = threadIdx.x + 256 * r;
-    if (q < nqp) rho[cell * nqp + q] = racc[r];
+    if (q < nqp) rho[cell * nqp + q] = (accumulate ? rho[cell * nqp + q] : 0.0) + racc[r];
   }
 }
 
@@ -671,13 +684,14 @@ extern "C" efe_status efe_scf_step(efe_ctx *c, double *V, int32_t N, int64_t ld,
       cols.push_back(j);
       max_occ_res = std::max(max_occ_res, resh[j]);
     }
+  // output density, column chunk by column chunk (occupied columns only)
   int32_t *dcols;
   double *Xh;
   if ((st = efe_ws(c, 31, std::max<size_t>(cols.size(), 1) * 4, (void **)&dcols))) return st;
-  if ((st = efe_ws(c, 0, (size_t)c->n_nodes * N * 8, (void **)&Xh))) return st;
-  if (!cols.empty())
-    HIPCHK(c, hipMemcpyAsync(dcols, cols.data(), cols.size() * 4, hipMemcpyHostToDevice, c->stream));
-  if ((st = efe_transform_cfe(c, V, ld, Xh, N, N))) return st;
+  if ((st = efe_ws(c, 0, (size_t)c->n_nodes * std::min<int32_t>(N, EFE_COL_CHUNK) * 8,
+                   (void **)&Xh)))
+    return st;
+  std::vector<int32_t> rel(cols.size());   // read by async copies until the sync below
   {
     const MeshGeo g = mesh_geo(c);
     EnrParam e;
@@ -686,11 +700,28 @@ extern "C" efe_status efe_scf_step(efe_ctx *c, double *V, int32_t N, int64_t ld,
     e.alpha = c->enr_alpha;
     e.rc = c->enr_rcut;
     e.t = c->enr_t;
-    k_density<<<c->n_cells, 256, 0, c->stream>>>(g, e, c->d_xq1, c->d_c2g, c->d_N3, Xh, N,
-                                                 V + c->n_nodes * ld, ld, dcols, (int)cols.size(),
-                                                 s.f, s.cell_ptr, s.cell_atom, c->d_xyz, c->d_nu,
-                                                 s.rho_out);
-    HIPCHK(c, hipGetLastError());
+    size_t done = 0;
+    bool first = true;
+    for (int32_t j0 = 0; j0 < N; j0 += EFE_COL_CHUNK) {
+      const int32_t nc = std::min<int32_t>(EFE_COL_CHUNK, N - j0);
+      size_t k0 = done;
+      while (done < cols.size() && cols[done] < j0 + nc) {
+        rel[done] = cols[done] - j0;
+        ++done;
+      }
+      const int nocc = (int)(done - k0);
+      if (nocc == 0 && !first) continue;
+      if (nocc)
+        HIPCHK(c, hipMemcpyAsync(dcols + k0, rel.data() + k0, nocc * 4, hipMemcpyHostToDevice,
+                                 c->stream));
+      if ((st = efe_transform_cfe(c, V + j0, ld, Xh, nc, nc))) return st;
+      k_density<<<c->n_cells, 256, 0, c->stream>>>(g, e, c->d_xq1, c->d_c2g, c->d_N3, Xh, nc,
+                                                   V + c->n_nodes * ld + j0, ld, dcols + k0, nocc,
+                                                   s.f + j0, s.cell_ptr, s.cell_atom, c->d_xyz,
+                                                   c->d_nu, s.rho_out, first ? 0 : 1);
+      HIPCHK(c, hipGetLastError());
+      first = false;
+    }
   }
   HIPCHK(c, hipStreamSynchronize(c->stream));
   const double t_dens = ms_since(t2);

@@ -251,6 +251,22 @@ __global__ void k_to_node_major(int64_t nnz, int nf, const int32_t *__restrict__
   dst[i] = src[(int64_t)nm_src[i / nf] * nf + i % nf];
 }
 
+// group-major copy: dst[(slot nf + k) 8 + n % 8] = src[nm_src[e] nf + k] for
+// every node-major entry e of node n (slot = its atom's place in the union of
+// the atoms of the 8-node group of n); entries not written stay zero
+__global__ void k_to_group_major(int64_t n_nodes, int nf, const int32_t *__restrict__ nm_ptr,
+                                 const int32_t *__restrict__ nm_src,
+                                 const int32_t *__restrict__ nm_gslot,
+                                 const double *__restrict__ src, double *__restrict__ dst) {
+  const int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (n >= n_nodes) return;
+  const int j = (int)(n & 7);
+  for (int32_t e = nm_ptr[n]; e < nm_ptr[n + 1]; ++e) {
+    const int64_t slot = nm_gslot[e], s0 = (int64_t)nm_src[e] * nf;
+    for (int k = 0; k < nf; ++k) dst[(slot * nf + k) * 8 + j] = src[s0 + k];
+  }
+}
+
 // Per (cell, I, J): M[I k][J l] += sum_q W phi_Ik phi_Jl and, with KIN,
 // H[I k][J l] += 1/2 sum_q W grad phi_Ik . grad phi_Jl; without KIN the
 // weight carries the potential: H[I k][J l] += sum_q W v phi_Ik phi_Jl.
@@ -619,8 +635,13 @@ efe_status efe_build_enrichment(efe_ctx *c) {
   if ((s = efe_alloc(c, (void **)&c->d_C_am, ns * 8))) return s;
   if ((s = efe_alloc(c, (void **)&c->d_Bkin_am, ns * 8))) return s;
   if ((s = efe_alloc(c, (void **)&c->d_B_am, ns * 8))) return s;
-  if ((s = efe_alloc(c, (void **)&c->d_C_nm, c->nnz_nm * nf * 8))) return s;
-  if ((s = efe_alloc(c, (void **)&c->d_B_nm, c->nnz_nm * nf * 8))) return s;
+  const int64_t ng = c->n_gslots * nf * 8;
+  if ((s = efe_alloc(c, (void **)&c->d_Cg, ng * 8))) return s;
+  if ((s = efe_alloc(c, (void **)&c->d_Bg, ng * 8))) return s;
+  if (ng) {
+    HIPCHK(c, hipMemsetAsync(c->d_Cg, 0, ng * 8, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->d_Bg, 0, ng * 8, c->stream));
+  }
   if ((s = efe_alloc(c, (void **)&c->d_Mpp, ne * ne * 8))) return s;
   if ((s = efe_alloc(c, (void **)&c->d_Mee, ne * ne * 8))) return s;
   if ((s = efe_alloc(c, (void **)&c->d_Hpp_kin, ne * ne * 8))) return s;
@@ -640,8 +661,8 @@ efe_status efe_build_enrichment(efe_ctx *c) {
         c->d_pair_cell, c->d_pair_lmap, nullptr, c->d_b_am, c->d_Bkin_am);
     k_scale_by_minv<<<cdiv(ns, 256), 256, 0, c->stream>>>(c->n_snodes, nf, c->d_snode, c->d_minv,
                                                           c->d_b_am, c->d_C_am);
-    k_to_node_major<<<cdiv(c->nnz_nm * nf, 256), 256, 0, c->stream>>>(c->nnz_nm, nf, c->d_nm_src,
-                                                                      c->d_C_am, c->d_C_nm);
+    k_to_group_major<<<cdiv(c->n_nodes, 256), 256, 0, c->stream>>>(
+        c->n_nodes, nf, c->d_nm_ptr, c->d_nm_src, c->d_nm_gslot, c->d_C_am, c->d_Cg);
     if (c->ntrip > 0)
       k_enr_pp<true><<<c->ntrip, 128, 0, c->stream>>>(g, e, c->d_xq1, c->d_W3, c->d_xyz, c->d_nu,
                                                       c->d_trip, nullptr, ne, c->d_Mpp,
@@ -726,8 +747,8 @@ efe_status efe_build_operators(efe_ctx *c, const double *vq, int precisions) {
     k_enr_pair_proj<false><<<c->npairs, 256, 0, c->stream>>>(
         g, e, c->d_xq1, c->d_W3, c->d_N3, c->d_G3, c->d_xyz, c->d_nu, c->d_pair_atom,
         c->d_pair_cell, c->d_pair_lmap, c->d_vq, c->d_B_am, nullptr);
-    k_to_node_major<<<cdiv(c->nnz_nm * nf, 256), 256, 0, c->stream>>>(c->nnz_nm, nf, c->d_nm_src,
-                                                                      c->d_B_am, c->d_B_nm);
+    k_to_group_major<<<cdiv(c->n_nodes, 256), 256, 0, c->stream>>>(
+        c->n_nodes, nf, c->d_nm_ptr, c->d_nm_src, c->d_nm_gslot, c->d_B_am, c->d_Bg);
     k_copy<<<cdiv(ne * ne, 256), 256, 0, c->stream>>>(ne * ne, c->d_Hpp_kin, c->d_Hpp);
     if (c->ntrip > 0)
       k_enr_pp<false><<<c->ntrip, 128, 0, c->stream>>>(g, e, c->d_xq1, c->d_W3, c->d_xyz,

@@ -360,14 +360,18 @@ class Context:
         return rep.as_dict()
 
 
-def scf_run(ctx, V, lam, v0, degree, tol=1e-5, max_iter=50, **kw):
-    """Drive efe_scf_step until |E_k - E_{k-1}| / N_atoms < tol; returns the
-    list of step reports."""
+def scf_run(ctx, V, lam, v0, degree, tol=1e-5, max_iter=50, rho_tol=1e-5, **kw):
+    """Drive efe_scf_step until |E_k - E_{k-1}| / N_atoms < tol and the
+    density residual ||rho_out - rho_in||_2 per electron is below rho_tol
+    (None: energy test only).  The energy alone can stall for a step while
+    the density is still far from self-consistent, so both are required.
+    Returns the list of step reports."""
     hist = []
     for it in range(max_iter):
         rep = ctx.scf_step(V, lam, v0, degree, **kw)
         hist.append(rep)
-        if it > 0 and abs(rep["dE"]) / max(ctx.natoms, 1) < tol:
+        if (it > 0 and abs(rep["dE"]) / max(ctx.natoms, 1) < tol and
+                (rho_tol is None or rep["drho"] / max(rep["n_el"], 1e-300) < rho_tol)):
             break
     return hist
 

@@ -55,6 +55,14 @@ def random_block(rows, ncols, seed):
     return rng.uniform(-1.0, 1.0, size=(rows, ncols))
 
 
+def random_block_rows(rows, ncols, seed, chunk_rows):
+    """The rows of random_block(rows, ncols, seed) in consecutive chunks of
+    chunk_rows (same values: one generator drawn in row-major order)."""
+    rng = np.random.default_rng(seed)
+    for r0 in range(0, rows, chunk_rows):
+        yield r0, rng.uniform(-1.0, 1.0, size=(min(chunk_rows, rows - r0), ncols))
+
+
 def random_vector(rows, seed):
     return np.random.default_rng(seed).uniform(-1.0, 1.0, size=rows)
 

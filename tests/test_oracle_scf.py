@@ -43,6 +43,19 @@ def test_fermi_level():
     assert np.allclose(f, [1, 1, 0, 0, 0, 0], atol=1e-12)
 
 
+def test_fermi_level_inside_a_wide_gap():
+    """Gap of 3 Ha at kT = 1e-2 Ha: 2 sum f is flat to rounding across it
+    (tails near 1e-65), yet mu is fixed by the tails.  Two states at -1 (full)
+    and one at +2 (empty), N_e = 4: the tails balance when
+    exp(-(2 - mu)/kT) = 2 exp(-(mu + 1)/kT), i.e. mu = 1/2 + kT ln(2)/2; a
+    symmetric gap puts mu in its middle."""
+    kT = 1e-2
+    mu, f = scf.fermi_level(np.array([-1.0, -1.0, 2.0]), 4.0, kT)
+    assert mu == pytest.approx(0.5 + 0.5 * kT * np.log(2.0), abs=1e-12)
+    mu, _ = scf.fermi_level(np.array([-1.0] * 4 + [1.0] * 4), 8.0, kT)
+    assert abs(mu) < 1e-12
+
+
 def _radial(fn, a=0.0, b=np.inf):
     return si.quad(fn, a, b, limit=400, epsabs=1e-14, epsrel=1e-13)[0]
 
