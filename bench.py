@@ -67,6 +67,36 @@ def cpu_baseline(w):
                       f"setup {t_setup:.1f} s excluded, apply {t:.2f} s"}
 
 
+def profile_applies(w, prec, k):
+    """A short program for hardware-counter runs: K H^E applies of the
+    workload's block under the local pseudopotential, then one plain device
+    copy of 1 GiB."""
+    import torch
+    from paper_2607_06848_amd import efe
+    from paper_2607_06848_amd import workloads as wl
+    ctx = efe.Context(w)
+    vq = ctx.local_potential()
+    ctx.set_potential(vq, precisions=(1 << efe.EFE_FP32) | (1 << efe.EFE_BF16))
+    N = w["nvec"]
+    X = torch.from_numpy(wl.random_block(ctx.rows, N, w["v0_seed"])).cuda()
+    Y = torch.empty_like(X)
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    for _ in range(k):
+        ctx.apply_H_prec(X, prec, Y)
+    n, ms = ctx.timing_get("cell")
+    na, msa = ctx.timing_get("apply")
+    ctx.timing(False)
+    log(f"{k} applies: cell launches {n} ({ms / max(n, 1):.3f} ms avg), "
+        f"apply {msa / max(na, 1):.3f} ms avg")
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    log("copied 1 GiB (read 1 GiB, write 1 GiB)")
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,6 +106,11 @@ def main():
     ap.add_argument("--workload", default="c64")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-scf", action="store_true", help="skip the time-to-SCF runs")
+    ap.add_argument("--profile-applies", type=int, default=0, metavar="K",
+                    help="profiling mode: set up the workload with its local pseudopotential, "
+                         "run K H^E applies of the N-vector block in --prec, copy a 1 GiB buffer "
+                         "once (a plain copy of known size for counter calibration), print "
+                         "timings and exit without the JSON line")
     ap.add_argument("--model", default=os.path.join(ROOT, "paper_2607_06848_amd", "weights",
                                                     "density_c64.npz"),
                     help="trained initial-density network for the mixed + learned SCF run")
@@ -93,6 +128,9 @@ def main():
     N, deg = w["nvec"], w["degree"]
     prec = PREC[args.prec]
     log("workload", args.workload, "N", N, "degree", deg, "filter precision", args.prec)
+    if args.profile_applies:
+        profile_applies(w, prec, args.profile_applies)
+        return
 
     def new_run():
         ctx = efe.Context(w)

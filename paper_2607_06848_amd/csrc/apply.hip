@@ -17,6 +17,20 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // columns per lane (x 64) of the row-reduction kernels
 constexpr int POST_Q = 3;
 
+// nblk consecutive blocks of work in eight contiguous ranges, one per XCD
+static XcdSplit xcd_ranges(int64_t nblk) {
+  XcdSplit x;
+  for (int i = 0; i <= 8; ++i) x.off[i] = nblk * i / 8;
+  return x;
+}
+
+// block index of the calling work-group under an XcdSplit, or -1
+__device__ inline int64_t xcd_block(const XcdSplit &x) {
+  const int xcd = blockIdx.x % 8;
+  const int64_t i = x.off[xcd] + blockIdx.x / 8;
+  return i < x.off[xcd + 1] ? i : -1;
+}
+
 // ------------------------------------------------------------------ pre
 // One wave per group of 8 consecutive nodes, one lane per column (up to 192
 // columns per pass, three per lane).  For every atom of the group's union
@@ -33,8 +47,10 @@ __global__ __launch_bounds__(256) void k_pre(int64_t n_nodes, int ncols, const d
                                              const double *__restrict__ Cg,
                                              const double *__restrict__ Bg, int nf,
                                              double *__restrict__ Xh, int64_t ldh,
-                                             double *Y, int64_t ldy) {
-  const int64_t grp = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + threadIdx.x / 64));
+                                             double *Y, int64_t ldy, XcdSplit xs) {
+  const int64_t blk = xcd_block(xs);
+  if (blk < 0) return;
+  const int64_t grp = blk * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
   const int lane = threadIdx.x % 64;
   const int64_t n0 = grp * 8;
   if (n0 >= n_nodes) return;
@@ -240,19 +256,17 @@ __global__ __launch_bounds__(256) void k_cell2(int ncells, int nparts,
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) ok[v] = ok[v] && minv[node[v]] != 0.0;
-    double yv[4][CBM];
 #pragma unroll
-    for (int v = 0; v < 4; ++v)
+    for (int v = 0; v < 4; ++v) {
+      double yv[CBM];
 #pragma unroll
-      for (int cb = 0; cb < CBM; ++cb)
-        yv[v][cb] = Y[node[v] * ldy + min(cb * 16 + li, ncols - 1)];
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
+      for (int cb = 0; cb < CBM; ++cb) yv[cb] = Y[node[v] * ldy + min(cb * 16 + li, ncols - 1)];
 #pragma unroll
       for (int cb = 0; cb < CBM; ++cb) {
         const int col = cb * 16 + li;
-        if (ok[v] && cb < CB && col < ncols) Y[node[v] * ldy + col] = yv[v][cb] + (double)acc[r][cb][v];
+        if (ok[v] && cb < CB && col < ncols) Y[node[v] * ldy + col] = yv[cb] + (double)acc[r][cb][v];
       }
+    }
   }
 }
 
@@ -325,13 +339,16 @@ __global__ __launch_bounds__(256) void k_cell_bf16(int ncells, int ntiles,
 // they read are shared through the caches.  Waves take one support node at a
 // time (wave-uniform) for up to 192 columns, three per lane.
 __global__ __launch_bounds__(256) void k_kb_project(int ncols, const int32_t *__restrict__ items,
+                                                    XcdSplit xs,
                                                     const int32_t *__restrict__ kbnode,
                                                     const double *__restrict__ Pc,
                                                     const double *__restrict__ Xh, int64_t ldh,
                                                     const double *__restrict__ D,
                                                     double *__restrict__ W) {
   __shared__ double red[3][64 * POST_Q];
-  const int32_t *it = items + 3 * (int64_t)blockIdx.x;
+  const int64_t item = xcd_block(xs);
+  if (item < 0) return;
+  const int32_t *it = items + 3 * item;
   const int I = it[0];
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
   const int lane = threadIdx.x % 64;
@@ -382,8 +399,11 @@ __global__ __launch_bounds__(256) void k_kb_expand(int64_t n_nodes, int ncols,
                                                    const int32_t *__restrict__ kbnm_atom,
                                                    const double *__restrict__ Pc_nm,
                                                    const double *__restrict__ W,
-                                                   double *__restrict__ Y, int64_t ldy) {
-  const int64_t j = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
+                                                   double *__restrict__ Y, int64_t ldy,
+                                                   XcdSplit xs) {
+  const int64_t blk = xcd_block(xs);
+  if (blk < 0) return;
+  const int64_t j = blk * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
   if (j >= n_nodes) return;
   const int lane = threadIdx.x % 64;
   const int32_t e0 = kbnm_ptr[j], e1 = kbnm_ptr[j + 1];
@@ -413,7 +433,7 @@ __global__ __launch_bounds__(256) void k_kb_expand(int64_t n_nodes, int ncols,
 // cache) for up to 192 columns, three per lane; the four waves' sums meet in
 // LDS and are added to Y^E once per item.
 __global__ __launch_bounds__(256) void k_enr_post(int nf, int ncols,
-                                                  const int32_t *__restrict__ items,
+                                                  const int32_t *__restrict__ items, XcdSplit xs,
                                                   const int32_t *__restrict__ snode,
                                                   const double *__restrict__ B_am,
                                                   const double *__restrict__ C_am,
@@ -421,7 +441,9 @@ __global__ __launch_bounds__(256) void k_enr_post(int nf, int ncols,
                                                   const double *__restrict__ Y, int64_t ldy,
                                                   double *__restrict__ YE, int64_t lde) {
   __shared__ double red[3][9][64 * POST_Q];
-  const int32_t *it = items + 3 * (int64_t)blockIdx.x;
+  const int64_t item = xcd_block(xs);
+  if (item < 0) return;
+  const int32_t *it = items + 3 * item;
   const int I = it[0];
   const int32_t s0 = it[1], s1 = it[2];
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
@@ -535,9 +557,10 @@ efe_status efe_apply_H_internal(efe_ctx *c, const double *XC, int64_t ldx, const
   // pre: Xh and Y^C = B^T X^E
   {
     const int t = efe_timer_begin(c, EFE_T_PRE);
-    k_pre<<<cdiv(c->n_nodes, 32), 256, 0, c->stream>>>(c->n_nodes, ncols, XC, ldx, scale,
-                                                       c->d_minv, XE, lde, c->d_g_ptr, c->d_g_atom,
-                                                       c->d_Cg, c->d_Bg, nf, Xh, ldh, Y, ldy);
+    const XcdSplit xs = xcd_ranges(cdiv(c->n_nodes, 32));
+    k_pre<<<8 * xs.max_len(), 256, 0, c->stream>>>(c->n_nodes, ncols, XC, ldx, scale, c->d_minv,
+                                                   XE, lde, c->d_g_ptr, c->d_g_atom, c->d_Cg,
+                                                   c->d_Bg, nf, Xh, ldh, Y, ldy, xs);
     efe_timer_end(c, EFE_T_PRE, t);
   }
   // projector coefficients
@@ -545,9 +568,11 @@ efe_status efe_apply_H_internal(efe_ctx *c, const double *XC, int64_t ldx, const
     k_kb_w_pphi<<<cdiv((int64_t)c->nproj * ncols, 256), 256, 0, c->stream>>>(
         c->nproj, ncols, c->n_enr, c->d_Pphi, XE, lde, c->d_D, W);
     if (c->n_kb_items) {
-      dim3 grd(c->n_kb_items, cdiv(ncols, 64 * POST_Q));
-      k_kb_project<<<grd, 256, 0, c->stream>>>(ncols, c->d_kb_items, c->d_kbnode, c->d_Pc_am, Xh,
-                                               ldh, c->d_D, W);
+      XcdSplit xs;
+      for (int i = 0; i <= 8; ++i) xs.off[i] = c->kb_items_off[i];
+      dim3 grd(8 * xs.max_len(), cdiv(ncols, 64 * POST_Q));
+      k_kb_project<<<grd, 256, 0, c->stream>>>(ncols, c->d_kb_items, xs, c->d_kbnode, c->d_Pc_am,
+                                               Xh, ldh, c->d_D, W);
     }
   }
   // cell GEMM, colour by colour
@@ -571,8 +596,9 @@ efe_status efe_apply_H_internal(efe_ctx *c, const double *XC, int64_t ldx, const
     }
   }
   if (c->nproj) {
-    k_kb_expand<<<cdiv(c->n_nodes, 4), 256, 0, c->stream>>>(c->n_nodes, ncols, c->d_kbnm_ptr,
-                                                            c->d_kbnm_atom, c->d_Pc_nm, W, Y, ldy);
+    const XcdSplit xs = xcd_ranges(cdiv(c->n_nodes, 4));
+    k_kb_expand<<<8 * xs.max_len(), 256, 0, c->stream>>>(c->n_nodes, ncols, c->d_kbnm_ptr,
+                                                         c->d_kbnm_atom, c->d_Pc_nm, W, Y, ldy, xs);
   }
   // enrichment rows
   const int t_post = efe_timer_begin(c, EFE_T_POST);
@@ -585,8 +611,10 @@ efe_status efe_apply_H_internal(efe_ctx *c, const double *XC, int64_t ldx, const
                       1.0, YE, ldy)))
       return s;
     if (c->n_enr_items) {
-      dim3 grd(c->n_enr_items, cdiv(ncols, 64 * POST_Q));
-      k_enr_post<<<grd, 256, 0, c->stream>>>(nf, ncols, c->d_enr_items, c->d_snode, c->d_B_am,
+      XcdSplit xs;
+      for (int i = 0; i <= 8; ++i) xs.off[i] = c->enr_items_off[i];
+      dim3 grd(8 * xs.max_len(), cdiv(ncols, 64 * POST_Q));
+      k_enr_post<<<grd, 256, 0, c->stream>>>(nf, ncols, c->d_enr_items, xs, c->d_snode, c->d_B_am,
                                              c->d_C_am, Xh, ldh, Y, ldy, YE, ldy);
     }
   }
@@ -599,10 +627,10 @@ efe_status efe_apply_H_internal(efe_ctx *c, const double *XC, int64_t ldx, const
 efe_status efe_transform_cfe(efe_ctx *c, const double *X, int64_t ldx, double *Xh, int64_t ldh,
                              int ncols) {
   if (ncols <= 0) return EFE_OK;
-  k_pre<<<cdiv(c->n_nodes, 32), 256, 0, c->stream>>>(c->n_nodes, ncols, X, ldx, nullptr, c->d_minv,
-                                                     X + c->n_nodes * ldx, ldx, c->d_g_ptr,
-                                                     c->d_g_atom, c->d_Cg, c->d_Bg, c->nf, Xh, ldh,
-                                                     nullptr, 0);
+  const XcdSplit xs = xcd_ranges(cdiv(c->n_nodes, 32));
+  k_pre<<<8 * xs.max_len(), 256, 0, c->stream>>>(c->n_nodes, ncols, X, ldx, nullptr, c->d_minv,
+                                                 X + c->n_nodes * ldx, ldx, c->d_g_ptr, c->d_g_atom,
+                                                 c->d_Cg, c->d_Bg, c->nf, Xh, ldh, nullptr, 0, xs);
   HIPCHK(c, hipGetLastError());
   return EFE_OK;
 }

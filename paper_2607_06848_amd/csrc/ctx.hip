@@ -180,11 +180,14 @@ static void build_support(const efe_ctx *c, double rc, SupportTables &T) {
 
 // Work items of the atom-major reductions over support nodes: every atom's
 // (node-sorted) support list cut at multiples of `region` node indices and
-// at `maxlen` entries, as (atom, first, end) triples ordered by region, so
-// that consecutive work-groups read the same rows for different atoms.
-static void build_items(int natoms, const std::vector<int32_t> &ptr,
+// at `maxlen` entries, as (atom, first, end) triples.  The regions are dealt
+// to the eight XCDs in contiguous ranges and each XCD's items are stored
+// together (region by region), so that the items of a region run on one XCD
+// and re-read its rows from that XCD's L2.  items_off[x] .. items_off[x+1]
+// are XCD x's items.
+static void build_items(int natoms, int64_t n_nodes, const std::vector<int32_t> &ptr,
                         const std::vector<int32_t> &snode, int32_t region, int32_t maxlen,
-                        std::vector<int32_t> &items) {
+                        std::vector<int32_t> &items, int64_t items_off[9]) {
   struct It { int32_t reg, atom, s0, s1; };
   std::vector<It> v;
   for (int I = 0; I < natoms; ++I) {
@@ -198,12 +201,19 @@ static void build_items(int natoms, const std::vector<int32_t> &ptr,
     }
   }
   std::stable_sort(v.begin(), v.end(), [](const It &a, const It &b) { return a.reg < b.reg; });
+  const int64_t nreg = std::max<int64_t>(1, cdiv(n_nodes, region));
   items.clear();
-  for (const It &x : v) {
-    items.push_back(x.atom);
-    items.push_back(x.s0);
-    items.push_back(x.s1);
+  size_t k = 0;
+  for (int x = 0; x < 8; ++x) {
+    items_off[x] = (int64_t)items.size() / 3;
+    while (k < v.size() && std::min<int64_t>(7, (int64_t)v[k].reg * 8 / nreg) == x) {
+      items.push_back(v[k].atom);
+      items.push_back(v[k].s0);
+      items.push_back(v[k].s1);
+      ++k;
+    }
   }
+  items_off[8] = (int64_t)items.size() / 3;
 }
 
 // (cell, I, J) for every cell and every pair of atoms from lists A and B whose
@@ -350,7 +360,7 @@ extern "C" efe_status efe_setup_mesh(const efe_mesh_desc *mesh, const efe_system
       HIPCHK(c, hipStreamSynchronize(c->stream));
     }
     std::vector<int32_t> items;
-    build_items(c->natoms, E.snode_ptr, E.snode, 4096, 1024, items);
+    build_items(c->natoms, c->n_nodes, E.snode_ptr, E.snode, 512, 1024, items, c->enr_items_off);
     c->n_enr_items = (int64_t)items.size() / 3;
     TRY(upload(c, &c->d_enr_items, items));
     std::vector<int32_t> trip;
@@ -370,7 +380,7 @@ extern "C" efe_status efe_setup_mesh(const efe_mesh_desc *mesh, const efe_system
     TRY(upload(c, &c->d_kbnm_atom, K.nm_atom));
     TRY(upload(c, &c->d_kbnm_src, K.nm_src));
     std::vector<int32_t> kbitems;
-    build_items(c->natoms, K.snode_ptr, K.snode, 4096, 1024, kbitems);
+    build_items(c->natoms, c->n_nodes, K.snode_ptr, K.snode, 512, 1024, kbitems, c->kb_items_off);
     c->n_kb_items = (int64_t)kbitems.size() / 3;
     TRY(upload(c, &c->d_kb_items, kbitems));
     std::vector<int32_t> kbtrip;

@@ -76,6 +76,7 @@ struct efe_ctx {
   double *d_Mee_inv = nullptr;                         // [natoms][nf][nf]
   // (atom, first, end) work items over the support lists, ordered by node region
   int64_t n_enr_items = 0, n_kb_items = 0;
+  int64_t enr_items_off[9] = {0}, kb_items_off[9] = {0};   // per-XCD ranges
   int32_t *d_enr_items = nullptr, *d_kb_items = nullptr;
 
   // Kleinman-Bylander projectors (one per atom)
@@ -141,6 +142,19 @@ void efe_set_global_error(const std::string &msg);
 efe_status efe_ws(efe_ctx *ctx, int slot, size_t bytes, void **p);
 
 static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Work-groups are dealt round-robin over the eight XCDs (block b runs on XCD
+// b % 8).  XcdSplit maps a block to (XCD, slot) and a per-XCD range of work
+// items, so that each XCD gets a contiguous share and its L2 sees only that
+// share's data.
+struct XcdSplit {
+  int64_t off[9];
+  __host__ __device__ int64_t max_len() const {
+    int64_t m = 0;
+    for (int x = 0; x < 8; ++x) m = off[x + 1] - off[x] > m ? off[x + 1] - off[x] : m;
+    return m;
+  }
+};
 
 // Column chunk of the wide-block passes (filter, Rayleigh-Ritz H V, density):
 // the cell GEMM's column tile, and the width the per-pass workspaces are

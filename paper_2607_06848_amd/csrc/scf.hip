@@ -415,9 +415,21 @@ __global__ void k_sub(int64_t n, const double *__restrict__ a, const double *__r
 }
 
 // small dense solve A g = r (k x k, partial pivoting, one thread)
+// slot j <- slot j + 1 for j < m, element by element (each thread reads a
+// slot before it overwrites it, so the overlapping shift is safe)
+__global__ void k_shift_history(int64_t n, int m, double *__restrict__ H) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int j = 0; j < m; ++j) H[(int64_t)j * n + i] = H[(int64_t)(j + 1) * n + i];
+}
+
+// Solve A g = r for the symmetric k x k matrix whose lower triangle is given
+// (Gaussian elimination with partial pivoting).
 __global__ void k_small_solve(int k, double *__restrict__ A, double *__restrict__ r,
                               double *__restrict__ g) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int i = 0; i < k; ++i)
+    for (int j = i + 1; j < k; ++j) A[i * k + j] = A[j * k + i];
   for (int c = 0; c < k; ++c) {
     int piv = c;
     for (int i = c + 1; i < k; ++i)
@@ -773,9 +785,9 @@ extern "C" efe_status efe_scf_step(efe_ctx *c, double *V, int32_t N, int64_t ld,
     s.nhist = 0;
   }
   double *HX = s.hist, *HF = s.hist + (int64_t)(m + 1) * nq;
-  if (s.nhist == m + 1) {   // drop the oldest entry
-    HIPCHK(c, hipMemcpyAsync(HX, HX + nq, (size_t)m * nq * 8, hipMemcpyDeviceToDevice, c->stream));
-    HIPCHK(c, hipMemcpyAsync(HF, HF + nq, (size_t)m * nq * 8, hipMemcpyDeviceToDevice, c->stream));
+  if (s.nhist == m + 1) {   // drop the oldest entry (the slots overlap: no memcpy)
+    k_shift_history<<<cdiv(nq, T), T, 0, c->stream>>>(nq, m, HX);
+    k_shift_history<<<cdiv(nq, T), T, 0, c->stream>>>(nq, m, HF);
     s.nhist = m;
   }
   const int k = s.nhist;
@@ -798,8 +810,6 @@ extern "C" efe_status efe_scf_step(efe_ctx *c, double *V, int32_t N, int64_t ld,
         k_sub<<<cdiv(nq, T), T, 0, c->stream>>>(nq, HF + (int64_t)(j + 1) * nq, HF + (int64_t)j * nq,
                                                 dfj);
         k_wdot<<<nb, 256, 0, c->stream>>>(nq, c->nqp, c->d_W3, dfi, dfj, A + i * k + j);
-        if (j != i)
-          k_wdot<<<nb, 256, 0, c->stream>>>(nq, c->nqp, c->d_W3, dfi, dfj, A + j * k + i);
       }
     }
     k_small_solve<<<1, 1, 0, c->stream>>>(k, A, rhs, gam);

@@ -51,8 +51,6 @@ def runs():
 
 
 def test_scf_energies_track_oracle(runs):
-    from oracle import scf
-    kT = 500 * scf.KB_HA_PER_K
     hist, reps, _, _ = runs
     for h, r in zip(hist, reps):
         dl = np.abs(r["lam"] - np.asarray(h["lam"]))
@@ -60,24 +58,11 @@ def test_scf_energies_track_oracle(runs):
              "dlam occupied", dl[:4].max(), "empty", dl[4:])
         assert abs(r["E"] - h["E"]) < 1e-8
         assert abs(r["F"] - h["F"]) < 1e-8
-        # Near convergence the Anderson normal equations dF^T W dF gamma =
-        # dF^T W F (both sides solve them by LU) grow ill-conditioned as the
-        # residual differences shrink and align, so rounding moves rho_in of
-        # the last steps (~1e-5 here) and with it every Ritz value; E, being
-        # stationary at self-consistency, moves by ~5e-9 only.  mu and the
-        # quantities below follow rho_in.  Before that, the Ritz values agree
-        # to rounding.
-        if h["drho"] > 1e-3:
-            assert dl.max() < 1e-10
-        assert abs(r["mu"] - h["mu"]) < 1e-4
-        # int rho_out weights every occupation by its state's Gauss-rule norm,
-        # so it moves with mu
-        assert abs(r["n_el"] - h["n_el"]) < 1e-9 + abs(r["mu"] - h["mu"]) / kT
-        # ||rho_out - rho_in|| near convergence is of the size of that shift
-        if h["drho"] > 1e-3:
-            assert abs(r["drho"] - h["drho"]) < 1e-8 * max(1.0, h["drho"])
-        else:
-            assert abs(r["drho"] - h["drho"]) < 0.2 * h["drho"]
+        assert dl.max() < 1e-10
+        # the Fermi level is resolved by its tails even inside the gap
+        assert abs(r["mu"] - h["mu"]) < 1e-9
+        assert abs(r["n_el"] - h["n_el"]) < 1e-9
+        assert abs(r["drho"] - h["drho"]) < 1e-8 * max(1.0, h["drho"])
         assert r["cg_iters"] > 0 or h["iter"] == 0
 
 
