@@ -106,6 +106,8 @@ def main():
     ap.add_argument("--workload", default="c64")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-scf", action="store_true", help="skip the time-to-SCF runs")
+    ap.add_argument("--scf-runs", default="fp64_sad,fp32_learned",
+                    help="time-to-SCF runs, comma separated <fp64|fp32>_<sad|learned>")
     ap.add_argument("--profile-applies", type=int, default=0, metavar="K",
                     help="profiling mode: set up the workload with its local pseudopotential, "
                          "run K H^E applies of the N-vector block in --prec, copy a 1 GiB buffer "
@@ -134,7 +136,9 @@ def main():
 
     def new_run():
         ctx = efe.Context(w)
-        V = torch.from_numpy(wl.random_block(ctx.rows, N, w["v0_seed"])).cuda()
+        V = torch.empty(ctx.rows, N, dtype=torch.float64, device="cuda")
+        for r0, blk in wl.random_block_rows(ctx.rows, N, w["v0_seed"], 1 << 18):
+            V[r0:r0 + len(blk)].copy_(torch.from_numpy(blk))
         lam = torch.zeros(N, dtype=torch.float64, device="cuda")
         v0 = torch.from_numpy(wl.random_vector(ctx.rows, 7)).cuda()
         return ctx, V, lam, v0
@@ -207,13 +211,14 @@ def main():
     }
     if not args.no_scf:
         from paper_2607_06848_amd import learned
-        runs = [("fp64_sad", PREC["fp64"], None)]
-        model = None
-        if os.path.exists(args.model):
-            model = learned.Model.load(args.model)
-            runs.append(("fp32_learned", PREC["fp32"], model))
-        else:
-            log(f"no density model at {args.model}: only the superposition-guess run")
+        model = learned.Model.load(args.model) if os.path.exists(args.model) else None
+        runs = []
+        for name in args.scf_runs.split(","):
+            p, g = name.split("_")
+            if g == "learned" and model is None:
+                log(f"no density model at {args.model}: skipping {name}")
+                continue
+            runs.append((name, PREC[p], model if g == "learned" else None))
         res = {}
         for name, prec_k, mdl in runs:
             log(f"time to SCF: {name}")
@@ -232,7 +237,7 @@ def main():
                          "guess": "learned" if mdl is not None and not fb else "superposition",
                          "filter_precision": "fp64" if prec_k == 0 else "fp32"}
             log(f"SCF {name}: {len(hist)} steps, {t_scf:.1f} s, E {hist[-1]['E']:.8f}")
-        if "fp32_learned" in res:
+        if "fp32_learned" in res and "fp64_sad" in res:
             a, b = res["fp64_sad"], res["fp32_learned"]
             res["speedup"] = a["seconds"] / b["seconds"]
             res["dE_per_atom"] = abs(a["E_Ha"] - b["E_Ha"]) / len(w["xyz"])

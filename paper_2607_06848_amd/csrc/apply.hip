@@ -17,13 +17,6 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // columns per lane (x 64) of the row-reduction kernels
 constexpr int POST_Q = 3;
 
-// nblk consecutive blocks of work in eight contiguous ranges, one per XCD
-static XcdSplit xcd_ranges(int64_t nblk) {
-  XcdSplit x;
-  for (int i = 0; i <= 8; ++i) x.off[i] = nblk * i / 8;
-  return x;
-}
-
 // block index of the calling work-group under an XcdSplit, or -1
 __device__ inline int64_t xcd_block(const XcdSplit &x) {
   const int xcd = blockIdx.x % 8;
@@ -47,10 +40,9 @@ __global__ __launch_bounds__(256) void k_pre(int64_t n_nodes, int ncols, const d
                                              const double *__restrict__ Cg,
                                              const double *__restrict__ Bg, int nf,
                                              double *__restrict__ Xh, int64_t ldh,
-                                             double *Y, int64_t ldy, XcdSplit xs) {
-  const int64_t blk = xcd_block(xs);
-  if (blk < 0) return;
-  const int64_t grp = blk * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
+                                             double *Y, int64_t ldy) {
+  const int64_t grp =
+      (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
   const int lane = threadIdx.x % 64;
   const int64_t n0 = grp * 8;
   if (n0 >= n_nodes) return;
@@ -399,11 +391,9 @@ __global__ __launch_bounds__(256) void k_kb_expand(int64_t n_nodes, int ncols,
                                                    const int32_t *__restrict__ kbnm_atom,
                                                    const double *__restrict__ Pc_nm,
                                                    const double *__restrict__ W,
-                                                   double *__restrict__ Y, int64_t ldy,
-                                                   XcdSplit xs) {
-  const int64_t blk = xcd_block(xs);
-  if (blk < 0) return;
-  const int64_t j = blk * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
+                                                   double *__restrict__ Y, int64_t ldy) {
+  const int64_t j =
+      (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
   if (j >= n_nodes) return;
   const int lane = threadIdx.x % 64;
   const int32_t e0 = kbnm_ptr[j], e1 = kbnm_ptr[j + 1];
@@ -557,10 +547,9 @@ efe_status efe_apply_H_internal(efe_ctx *c, const double *XC, int64_t ldx, const
   // pre: Xh and Y^C = B^T X^E
   {
     const int t = efe_timer_begin(c, EFE_T_PRE);
-    const XcdSplit xs = xcd_ranges(cdiv(c->n_nodes, 32));
-    k_pre<<<8 * xs.max_len(), 256, 0, c->stream>>>(c->n_nodes, ncols, XC, ldx, scale, c->d_minv,
-                                                   XE, lde, c->d_g_ptr, c->d_g_atom, c->d_Cg,
-                                                   c->d_Bg, nf, Xh, ldh, Y, ldy, xs);
+    k_pre<<<cdiv(c->n_nodes, 32), 256, 0, c->stream>>>(c->n_nodes, ncols, XC, ldx, scale,
+                                                       c->d_minv, XE, lde, c->d_g_ptr, c->d_g_atom,
+                                                       c->d_Cg, c->d_Bg, nf, Xh, ldh, Y, ldy);
     efe_timer_end(c, EFE_T_PRE, t);
   }
   // projector coefficients
@@ -596,9 +585,8 @@ efe_status efe_apply_H_internal(efe_ctx *c, const double *XC, int64_t ldx, const
     }
   }
   if (c->nproj) {
-    const XcdSplit xs = xcd_ranges(cdiv(c->n_nodes, 4));
-    k_kb_expand<<<8 * xs.max_len(), 256, 0, c->stream>>>(c->n_nodes, ncols, c->d_kbnm_ptr,
-                                                         c->d_kbnm_atom, c->d_Pc_nm, W, Y, ldy, xs);
+    k_kb_expand<<<cdiv(c->n_nodes, 4), 256, 0, c->stream>>>(c->n_nodes, ncols, c->d_kbnm_ptr,
+                                                            c->d_kbnm_atom, c->d_Pc_nm, W, Y, ldy);
   }
   // enrichment rows
   const int t_post = efe_timer_begin(c, EFE_T_POST);
@@ -627,10 +615,10 @@ efe_status efe_apply_H_internal(efe_ctx *c, const double *XC, int64_t ldx, const
 efe_status efe_transform_cfe(efe_ctx *c, const double *X, int64_t ldx, double *Xh, int64_t ldh,
                              int ncols) {
   if (ncols <= 0) return EFE_OK;
-  const XcdSplit xs = xcd_ranges(cdiv(c->n_nodes, 32));
-  k_pre<<<8 * xs.max_len(), 256, 0, c->stream>>>(c->n_nodes, ncols, X, ldx, nullptr, c->d_minv,
-                                                 X + c->n_nodes * ldx, ldx, c->d_g_ptr, c->d_g_atom,
-                                                 c->d_Cg, c->d_Bg, c->nf, Xh, ldh, nullptr, 0, xs);
+  k_pre<<<cdiv(c->n_nodes, 32), 256, 0, c->stream>>>(c->n_nodes, ncols, X, ldx, nullptr, c->d_minv,
+                                                     X + c->n_nodes * ldx, ldx, c->d_g_ptr,
+                                                     c->d_g_atom, c->d_Cg, c->d_Bg, c->nf, Xh, ldh,
+                                                     nullptr, 0);
   HIPCHK(c, hipGetLastError());
   return EFE_OK;
 }

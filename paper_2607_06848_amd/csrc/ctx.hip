@@ -180,11 +180,11 @@ static void build_support(const efe_ctx *c, double rc, SupportTables &T) {
 
 // Work items of the atom-major reductions over support nodes: every atom's
 // (node-sorted) support list cut at multiples of `region` node indices and
-// at `maxlen` entries, as (atom, first, end) triples.  The regions are dealt
-// to the eight XCDs in contiguous ranges and each XCD's items are stored
-// together (region by region), so that the items of a region run on one XCD
-// and re-read its rows from that XCD's L2.  items_off[x] .. items_off[x+1]
-// are XCD x's items.
+// at `maxlen` entries, as (atom, first, end) triples.  Region r goes to XCD
+// r % 8 (round robin keeps the dense middle of a cluster spread over all
+// XCDs) and each XCD's items are stored together, region by region, so that
+// the items of a region run on one XCD and re-read its rows from that XCD's
+// L2.  items_off[x] .. items_off[x+1] are XCD x's items.
 static void build_items(int natoms, int64_t n_nodes, const std::vector<int32_t> &ptr,
                         const std::vector<int32_t> &snode, int32_t region, int32_t maxlen,
                         std::vector<int32_t> &items, int64_t items_off[9]) {
@@ -200,17 +200,18 @@ static void build_items(int natoms, int64_t n_nodes, const std::vector<int32_t> 
       s = e;
     }
   }
-  std::stable_sort(v.begin(), v.end(), [](const It &a, const It &b) { return a.reg < b.reg; });
-  const int64_t nreg = std::max<int64_t>(1, cdiv(n_nodes, region));
+  (void)n_nodes;
+  std::stable_sort(v.begin(), v.end(), [](const It &a, const It &b) {
+    return a.reg % 8 != b.reg % 8 ? a.reg % 8 < b.reg % 8 : a.reg < b.reg;
+  });
   items.clear();
   size_t k = 0;
   for (int x = 0; x < 8; ++x) {
     items_off[x] = (int64_t)items.size() / 3;
-    while (k < v.size() && std::min<int64_t>(7, (int64_t)v[k].reg * 8 / nreg) == x) {
+    for (; k < v.size() && v[k].reg % 8 == x; ++k) {
       items.push_back(v[k].atom);
       items.push_back(v[k].s0);
       items.push_back(v[k].s1);
-      ++k;
     }
   }
   items_off[8] = (int64_t)items.size() / 3;

@@ -145,8 +145,7 @@ static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // Work-groups are dealt round-robin over the eight XCDs (block b runs on XCD
 // b % 8).  XcdSplit maps a block to (XCD, slot) and a per-XCD range of work
-// items, so that each XCD gets a contiguous share and its L2 sees only that
-// share's data.
+// items, so that a chosen set of items runs on one XCD and shares its L2.
 struct XcdSplit {
   int64_t off[9];
   __host__ __device__ int64_t max_len() const {
