@@ -148,7 +148,10 @@ def main():
     torch.cuda.synchronize()
     log(f"setup {time.perf_counter() - t0:.2f} s rows {ctx.rows} dof {ctx.n_dof} "
         f"enr {ctx.n_enr} cells {ctx.n_cells}")
-    kw = dict(prec=prec, passes_first=4, passes=1)
+    def on_pass(i, tf, tr):
+        log(f"  pass {i}: filter {tf:.0f} ms, Rayleigh-Ritz {tr:.0f} ms")
+
+    kw = dict(prec=prec, passes_first=4, passes=1, progress=on_pass)
     for i in range(args.warmup):
         r = ctx.scf_step(V, lam, v0, deg, **kw)
         log(f"warmup step {i}: E {r['E']:.8f} dE {r['dE']:.2e} filter {r['t_filter_ms']:.0f} ms")
@@ -158,6 +161,7 @@ def main():
     t0 = time.perf_counter()
     for i in range(args.steps):
         reps.append(ctx.scf_step(V, lam, v0, deg, **kw))
+        log(f"step {i}: E {reps[-1]['E']:.8f} dE {reps[-1]['dE']:.2e}")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ncell_l, cell_ms = ctx.timing_get("cell")
@@ -227,7 +231,9 @@ def main():
             t0 = time.perf_counter()
             fb, fac = mdl.apply(ctx) if mdl is not None else ctx.density_guess(None)
             hist = efe.scf_run(ctx, V, lam, v0, deg, tol=1e-5, max_iter=60, prec=prec_k,
-                               passes_first=4, passes=1)
+                               passes_first=4, passes=1, progress=on_pass,
+                               log=lambda i, r: log(f" {name} step {i}: E {r['E']:.8f} "
+                                                    f"dE {r['dE']:.2e} drho {r['drho']:.2e}"))
             torch.cuda.synchronize()
             t_scf = time.perf_counter() - t0
             ctx.close()

@@ -181,6 +181,11 @@ typedef struct {
   double cg_rtol;        /* Poisson CG relative residual */
   int32_t cg_maxit;
   int32_t lanczos_steps; /* spectrum bound per step */
+  /* optional: called on the host after every filter + Rayleigh-Ritz pass with
+   * the pass index, the pass's filter and Rayleigh-Ritz times (ms) and
+   * `progress_user` (progress reports of long steps); NULL: none */
+  void (*progress)(int32_t pass, double filter_ms, double rr_ms, void *user);
+  void *progress_user;
 } efe_scf_params;
 
 typedef struct {

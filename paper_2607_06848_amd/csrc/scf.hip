@@ -151,10 +151,11 @@ __global__ __launch_bounds__(256) void k_stiff_apply(int ncells, const int32_t *
                                                      const double *__restrict__ K,
                                                      const double *__restrict__ x,
                                                      const double *__restrict__ minv,
-                                                     double *__restrict__ y) {
+                                                     double *__restrict__ y,
+                                                     const double *__restrict__ done) {
   __shared__ double xs[EFE_MAXLOC];
   const int ci = blockIdx.x;
-  if (ci >= ncells) return;
+  if (ci >= ncells || (done && *done != 0.0)) return;
   const int64_t cell = cells[ci];
   for (int l = threadIdx.x; l < nloc; l += blockDim.x) {
     const int32_t node = c2g[cell * nloc + l];
@@ -414,7 +415,88 @@ __global__ void k_sub(int64_t n, const double *__restrict__ a, const double *__r
   if (i < n) c[i] = a[i] - b[i];
 }
 
-// small dense solve A g = r (k x k, partial pivoting, one thread)
+// ---- Poisson CG with its scalars on the device.  sc[0] r.z, sc[1] p.Ap,
+// sc[2] r.r, sc[3] new r.z, sc[4] done flag, sc[5] iterations, sc[6] the
+// squared stopping threshold.  Every kernel of an iteration returns at once
+// when the flag is set, so the host can queue iterations in batches and
+// still stop after the same iteration as a loop that tests r.r each time.
+__device__ inline double block_sum(double v, double *red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  return red[0];
+}
+
+__global__ void k_cg_zero(int64_t n, double *__restrict__ y, const double *__restrict__ sc) {
+  if (sc[4] != 0.0) return;
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) y[i] = 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_cg_pap(int64_t n, const double *__restrict__ p,
+                                                const double *__restrict__ Ap,
+                                                double *__restrict__ sc) {
+  __shared__ double red[256];
+  if (sc[4] != 0.0) return;
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    acc += p[i] * Ap[i];
+  const double t = block_sum(acc, red);
+  if (threadIdx.x == 0) atomicAdd(&sc[1], t);
+}
+
+// phi += alpha p, r -= alpha Ap, z = r / diag (interior), r.r and r.z
+__global__ __launch_bounds__(256) void k_cg_update(int64_t n, const double *__restrict__ p,
+                                                   const double *__restrict__ Ap,
+                                                   const double *__restrict__ d,
+                                                   const double *__restrict__ minv,
+                                                   double *__restrict__ phi, double *__restrict__ r,
+                                                   double *__restrict__ z, double *__restrict__ sc) {
+  __shared__ double red[256];
+  if (sc[4] != 0.0) return;
+  const double alpha = sc[0] / sc[1];
+  double rr = 0.0, rz = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    phi[i] += alpha * p[i];
+    const double ri = r[i] - alpha * Ap[i];
+    r[i] = ri;
+    const double zi = minv[i] == 0.0 ? 0.0 : ri / d[i];
+    z[i] = zi;
+    rr += ri * ri;
+    rz += ri * zi;
+  }
+  const double t1 = block_sum(rr, red);
+  __syncthreads();
+  const double t2 = block_sum(rz, red);
+  if (threadIdx.x == 0) {
+    atomicAdd(&sc[2], t1);
+    atomicAdd(&sc[3], t2);
+  }
+}
+
+__global__ void k_cg_pupdate(int64_t n, const double *__restrict__ z, double *__restrict__ p,
+                             const double *__restrict__ sc) {
+  if (sc[4] != 0.0) return;
+  const double beta = sc[3] / sc[0];
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = z[i] + beta * p[i];
+}
+
+__global__ void k_cg_next(double *__restrict__ sc) {
+  if (sc[4] != 0.0) return;
+  sc[5] += 1.0;
+  if (sc[2] <= sc[6]) sc[4] = 1.0;
+  sc[0] = sc[3];
+  sc[1] = 0.0;
+  sc[2] = 0.0;
+  sc[3] = 0.0;
+}
+
 // slot j <- slot j + 1 for j < m, element by element (each thread reads a
 // slot before it overwrites it, so the overlapping shift is safe)
 __global__ void k_shift_history(int64_t n, int m, double *__restrict__ H) {
@@ -528,13 +610,19 @@ static efe_status scf_init(efe_ctx *c) {
   return EFE_OK;
 }
 
-static efe_status stiff_apply(efe_ctx *c, const double *x, double *y) {
-  HIPCHK(c, hipMemsetAsync(y, 0, c->n_nodes * 8, c->stream));
+// y = K x on interior nodes; with `done` (device CG flag) every launch
+// returns at once when the flag is set
+static efe_status stiff_apply(efe_ctx *c, const double *x, double *y, const double *sc = nullptr) {
+  if (sc)
+    k_cg_zero<<<cdiv(c->n_nodes, 256), 256, 0, c->stream>>>(c->n_nodes, y, sc);
+  else
+    HIPCHK(c, hipMemsetAsync(y, 0, c->n_nodes * 8, c->stream));
   for (int col = 0; col < 8; ++col) {
     const int nc = c->colour_offsets[col + 1] - c->colour_offsets[col];
     if (!nc) continue;
     k_stiff_apply<<<nc, 256, 0, c->stream>>>(nc, c->d_colour_order + c->colour_offsets[col],
-                                             c->nloc, c->d_c2g, c->d_K, x, c->d_minv, y);
+                                             c->nloc, c->d_c2g, c->d_K, x, c->d_minv, y,
+                                             sc ? sc + 4 : nullptr);
   }
   HIPCHK(c, hipGetLastError());
   return EFE_OK;
@@ -577,23 +665,32 @@ static efe_status poisson(efe_ctx *c, const double *fq, const double *sub, doubl
     *iters = 0;
     return EFE_OK;
   }
-  while (sqrt(rr) > rtol * bn && it < maxit) {
-    if ((st = stiff_apply(c, p, Ap))) return st;
-    if ((st = dot_host(c, nn, p, Ap, &pAp))) return st;
-    const double alpha = rz / pAp;
-    k_axpby<<<cdiv(nn, T), T, 0, c->stream>>>(nn, alpha, p, 1.0, phi);
-    k_axpby<<<cdiv(nn, T), T, 0, c->stream>>>(nn, -alpha, Ap, 1.0, r);
-    if ((st = dot_host(c, nn, r, r, &rr))) return st;
-    k_precond<<<cdiv(nn, T), T, 0, c->stream>>>(nn, r, s.Kdiag, c->d_minv, z);
-    double rz_new;
-    if ((st = dot_host(c, nn, r, z, &rz_new))) return st;
-    k_axpby<<<cdiv(nn, T), T, 0, c->stream>>>(nn, 1.0, z, rz_new / rz, p);
-    rz = rz_new;
-    ++it;
+  (void)pAp;
+  // iterations in batches of 16 with the scalars on the device; the loop
+  // stops after the first iteration that meets sqrt(r.r) <= rtol |b|
+  double *sc = s.scal + 96;
+  const double init[7] = {rz, 0.0, 0.0, 0.0, sqrt(rr) > rtol * bn ? 0.0 : 1.0, 0.0,
+                          (rtol * bn) * (rtol * bn)};   // read by the copy until the sync below
+  HIPCHK(c, hipMemcpyAsync(sc, init, sizeof(init), hipMemcpyHostToDevice, c->stream));
+  const unsigned nb = (unsigned)std::min<int64_t>(cdiv(nn, T), 1024);
+  double hs[6] = {0, 0, 0, 0, 0, 0};
+  while (it < maxit) {
+    const int batch = std::min(16, maxit - it);
+    for (int q = 0; q < batch; ++q) {
+      if ((st = stiff_apply(c, p, Ap, sc))) return st;
+      k_cg_pap<<<nb, T, 0, c->stream>>>(nn, p, Ap, sc);
+      k_cg_update<<<nb, T, 0, c->stream>>>(nn, p, Ap, s.Kdiag, c->d_minv, phi, r, z, sc);
+      k_cg_pupdate<<<cdiv(nn, T), T, 0, c->stream>>>(nn, z, p, sc);
+      k_cg_next<<<1, 1, 0, c->stream>>>(sc);
+    }
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(hs, sc, 6 * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    it = (int)hs[5];
+    if (hs[4] != 0.0) break;
   }
-  HIPCHK(c, hipGetLastError());
   *iters = it;
-  if (it >= maxit) EFE_FAIL(c, EFE_ENOTCONV, "Poisson CG did not converge");
+  if (hs[4] == 0.0) EFE_FAIL(c, EFE_ENOTCONV, "Poisson CG did not converge");
   return EFE_OK;
 }
 
@@ -672,11 +769,14 @@ extern "C" efe_status efe_scf_step(efe_ctx *c, double *V, int32_t N, int64_t ld,
     auto ta = std::chrono::steady_clock::now();
     if ((st = efe_cheb_filter(c, V, lambda, N, ld, &cp))) return st;
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    t_filter += ms_since(ta);
+    const double tfl = ms_since(ta);
+    t_filter += tfl;
     ta = std::chrono::steady_clock::now();
     if ((st = efe_rayleigh_ritz(c, V, N, ld, lambda, res))) return st;
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    t_rr += ms_since(ta);
+    const double trr = ms_since(ta);
+    t_rr += trr;
+    if (prm->progress) prm->progress(pss, tfl, trr, prm->progress_user);
   }
   auto t2 = std::chrono::steady_clock::now();
   // 3. occupations and output density

@@ -49,7 +49,12 @@ class ScfParams(ctypes.Structure):
                 ("degree", ctypes.c_int32), ("prec", ctypes.c_int32), ("kT", ctypes.c_double),
                 ("mix_beta", ctypes.c_double), ("mix_history", ctypes.c_int32),
                 ("cg_rtol", ctypes.c_double), ("cg_maxit", ctypes.c_int32),
-                ("lanczos_steps", ctypes.c_int32)]
+                ("lanczos_steps", ctypes.c_int32), ("progress", ctypes.c_void_p),
+                ("progress_user", ctypes.c_void_p)]
+
+
+PROGRESS = ctypes.CFUNCTYPE(None, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                            ctypes.c_void_p)
 
 
 class ScfReport(ctypes.Structure):
@@ -349,11 +354,15 @@ class Context:
 
     def scf_step(self, V, lam, v0, degree, passes_first=4, passes=1, prec=EFE_FP64,
                  kT=500 * 3.166811563e-6, mix_beta=0.3, mix_history=8, cg_rtol=1e-12,
-                 cg_maxit=5000, lanczos_steps=20):
+                 cg_maxit=5000, lanczos_steps=20, progress=None):
+        """One SCF step; `progress(pass, filter_ms, rr_ms)` (optional) is called
+        after every filter + Rayleigh-Ritz pass."""
         n, ld = self._block(V)
+        cb = PROGRESS(lambda i, tf, tr, _u: progress(i, tf, tr)) if progress else None
         p = ScfParams(int(passes_first), int(passes), int(degree), int(prec), float(kT),
                       float(mix_beta), int(mix_history), float(cg_rtol), int(cg_maxit),
-                      int(lanczos_steps))
+                      int(lanczos_steps),
+                      ctypes.cast(cb, ctypes.c_void_p) if cb is not None else None, None)
         rep = ScfReport()
         self._check(lib().efe_scf_step(self.h, _ptr(V), n, ld, _ptr(lam), _ptr(v0),
                                        ctypes.byref(p), ctypes.byref(rep)))
@@ -365,11 +374,15 @@ def scf_run(ctx, V, lam, v0, degree, tol=1e-5, max_iter=50, rho_tol=1e-5, **kw):
     density residual ||rho_out - rho_in||_2 per electron is below rho_tol
     (None: energy test only).  The energy alone can stall for a step while
     the density is still far from self-consistent, so both are required.
+    `log(step, report)` (optional keyword) is called after every step.
     Returns the list of step reports."""
     hist = []
+    log = kw.pop("log", None)
     for it in range(max_iter):
         rep = ctx.scf_step(V, lam, v0, degree, **kw)
         hist.append(rep)
+        if log:
+            log(it, rep)
         if (it > 0 and abs(rep["dE"]) / max(ctx.natoms, 1) < tol and
                 (rho_tol is None or rep["drho"] / max(rep["n_el"], 1e-300) < rho_tol)):
             break
