@@ -30,10 +30,33 @@ sys.path.insert(0, ROOT)
 
 PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15, "hbm": 8.0e12}
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
+CELL_KERNEL = {"fp64": "k_cell2<double, 2, 10>", "fp32": "k_cell2<float, 3, 10>",
+               "bf16": "k_cell_bf16<32>"}
 
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (rocprofv3 FETCH_SIZE and WRITE_SIZE runs, each scaled by the same
+    counter's reading for a 1 GiB device copy), or None when the summary is
+    missing or was taken from a different source of the cell GEMM."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "cell_gemm_c64_traffic.json")
+    src = os.path.join(ROOT, "paper_2607_06848_amd", "csrc", "apply.hip")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+        with open(src, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    if k is None or rec.get("apply_hip_sha256") != sha:
+        return None
+    return k["read_bytes"] + k["write_bytes"]
 
 
 def cpu_baseline(w):
@@ -97,6 +120,48 @@ def profile_applies(w, prec, k):
     ctx.close()
 
 
+def precision_error(w):
+    """Differences between one FP64 and one FP32 SCF step from the same
+    start (superposition density, seeded block): occupied eigenvalues, the
+    output density (relative L2 over the Gauss points) and the energy."""
+    import torch
+    from paper_2607_06848_amd import efe
+    from paper_2607_06848_amd import workloads as wl
+    N, deg = w["nvec"], w["degree"]
+    out = {}
+    for name, p in (("fp64", PREC["fp64"]), ("fp32", PREC["fp32"])):
+        ctx = efe.Context(w)
+        V = torch.empty(ctx.rows, N, dtype=torch.float64, device="cuda")
+        for r0, blk in wl.random_block_rows(ctx.rows, N, w["v0_seed"], 1 << 18):
+            V[r0:r0 + len(blk)].copy_(torch.from_numpy(blk))
+        lam = torch.zeros(N, dtype=torch.float64, device="cuda")
+        v0 = torch.from_numpy(wl.random_vector(ctx.rows, 7)).cuda()
+        t0 = time.perf_counter()
+        rep = ctx.scf_step(V, lam, v0, deg, prec=p, passes_first=4, passes=1,
+                           progress=lambda i, tf, tr: log(f"  {name} pass {i}: filter {tf:.0f} ms"))
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        _, wq = ctx.quadrature()
+        out[name] = dict(E=rep["E"], lam=lam.cpu().numpy(), rho=ctx.get_density(1).cpu().numpy(),
+                         wq=wq.cpu().numpy(), seconds=dt)
+        log(f"{name}: step {dt:.1f} s, E {rep['E']:.8f}")
+        ctx.close()
+        del V
+        torch.cuda.empty_cache()
+    a, b = out["fp64"], out["fp32"]
+    ne = int(round(float(np.sum(w["Zs"])))) // 2
+    wq = a["wq"]
+    drho = np.sqrt(np.sum(wq * (b["rho"] - a["rho"]) ** 2) / np.sum(wq * a["rho"] ** 2))
+    print(json.dumps({"workload": w["name"], "natoms": len(w["xyz"]), "vectors": N,
+                      "step": "first SCF step: Rayleigh-Ritz of the seeded block + 4 passes",
+                      "seconds": {"fp64": a["seconds"], "fp32": b["seconds"]},
+                      "occupied_eigenvalue_max_abs_diff_Ha": float(
+                          np.abs(b["lam"][:ne] - a["lam"][:ne]).max()),
+                      "density_rel_L2_diff": float(drho),
+                      "energy_diff_Ha_per_atom": abs(b["E"] - a["E"]) / len(w["xyz"])}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -113,6 +178,10 @@ def main():
                          "run K H^E applies of the N-vector block in --prec, copy a 1 GiB buffer "
                          "once (a plain copy of known size for counter calibration), print "
                          "timings and exit without the JSON line")
+    ap.add_argument("--prec-error", action="store_true",
+                    help="one SCF step (Rayleigh-Ritz + first-step passes) in FP64 and in FP32 "
+                         "from the same start; print the eigenvalue, density and energy "
+                         "differences as one JSON line and exit")
     ap.add_argument("--model", default=os.path.join(ROOT, "paper_2607_06848_amd", "weights",
                                                     "density_c64.npz"),
                     help="trained initial-density network for the mixed + learned SCF run")
@@ -132,6 +201,9 @@ def main():
     log("workload", args.workload, "N", N, "degree", deg, "filter precision", args.prec)
     if args.profile_applies:
         profile_applies(w, prec, args.profile_applies)
+        return
+    if args.prec_error:
+        precision_error(w)
         return
 
     def new_run():
@@ -208,9 +280,9 @@ def main():
                    "filter_ms_per_pass": filt_ms / npass, "rr_ms": rr_ms / max(nrr, 1),
                    "h_apply_ms": app_ms / max(napp, 1),
                    "recurrence_ms": rec_ms / max(nrec, 1), "step_breakdown_ms": breakdown},
-        "roofline": {"bound": "mfma", "kernel": "k_cell (one colour pass of the cell GEMM)",
+        "roofline": {"bound": "mfma", "kernel": CELL_KERNEL[args.prec] + " (one colour pass)",
                      "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak, "traffic": measured_traffic(CELL_KERNEL[args.prec]),
                      "launch_ms": avg_cell_s * 1e3, "flops_per_launch": flops_per_launch},
     }
     if not args.no_scf:

@@ -273,7 +273,10 @@ efe_status efe_scf_step(efe_ctx *ctx, double *V, int32_t ncols, int64_t ld, doub
  * and their summed duration in milliseconds (synchronizes the stream):
  *   0 one colour pass of the cell GEMM   1 pre pass of an H apply
  *   2 enrichment rows of an H apply      3 residual recurrence update
- *   4 whole H apply                      5 whole Rayleigh-Ritz */
+ *   4 whole H apply                      5 whole Rayleigh-Ritz
+ *   6 colour pass, blocks of <= 16 vectors (e.g. the Lanczos vector)
+ *   7 whole H apply, blocks of <= 16 vectors
+ * Classes 0 and 4 count blocks wider than 16 vectors only. */
 efe_status efe_timing(efe_ctx *ctx, int32_t enable);
 efe_status efe_timing_get(efe_ctx *ctx, int32_t which, int64_t *launches, double *total_ms);
 

@@ -115,7 +115,9 @@ struct CellMfma;
 template <>
 struct CellMfma<double> {
   typedef v4d acc_t;
-  static constexpr int NCP = 176;   // LDS row stride: two 16-lane rows hit disjoint banks
+  // LDS row stride for NC columns: the two 16-lane rows of a half-wave read
+  // hit disjoint banks
+  static constexpr int ncp(int NC) { return NC == 16 ? 16 : NC + 16; }
   __device__ static inline acc_t op(double a, double b, acc_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
@@ -126,7 +128,9 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 template <>
 struct CellMfma<float> {
   typedef v4f acc_t;
-  static constexpr int NCP = 208;   // four 16-lane rows on disjoint banks
+  // LDS row stride for NC columns: the four 16-lane rows of a wave read hit
+  // disjoint banks
+  static constexpr int ncp(int NC) { return NC == 16 ? 16 : NC + 48; }
   __device__ static inline acc_t op(float a, float b, acc_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
@@ -134,9 +138,7 @@ struct CellMfma<float> {
   __device__ static inline int row(int v, int lk) { return 4 * lk + v; }
 };
 
-constexpr int CELL_CBM = 10;   // column blocks per launch (160 columns)
-
-template <typename T, int RBW>
+template <typename T, int RBW, int CBM>
 __global__ __launch_bounds__(256) void k_cell2(int ncells, int nparts,
                                                const int32_t *__restrict__ cells,
                                                const int32_t *__restrict__ c2g, int nloc, int RB,
@@ -146,8 +148,8 @@ __global__ __launch_bounds__(256) void k_cell2(int ncells, int nparts,
                                                const double *__restrict__ minv, int ncols) {
   typedef CellMfma<T> M;
   typedef typename M::acc_t acc_t;
-  constexpr int CBM = CELL_CBM, NC = CBM * 16, KC = 16, EPT = KC * NC / 256;
-  __shared__ T Xs[2][KC][M::NCP];
+  constexpr int NC = CBM * 16, KC = 16, EPT = KC * NC / 256;
+  __shared__ T Xs[2][KC][M::ncp(NC)];
   __shared__ int32_t gs[EFE_MAXLOC];   // the cell's node numbers
   const int b = blockIdx.x;
   const int xcd = b % 8, slot = b / 8;
@@ -509,22 +511,22 @@ __global__ void k_enr_block_apply(int natoms, int nf, int ncols, const double *_
 }
 
 // ------------------------------------------------------------------ launchers
-// Colour passes of the cell GEMM in column chunks of 160.
-template <typename T, int RBW>
+// Colour passes of the cell GEMM in column chunks of 16 CBM.
+template <typename T, int RBW, int CBM>
 static void launch_cell2(efe_ctx *c, const T *Ht, const double *Xh, int64_t ldh, double *Y,
                          int64_t ldy, int ncols) {
   const int nparts = (int)cdiv(c->RB, 4 * RBW);
-  for (int col0 = 0; col0 < ncols; col0 += 16 * CELL_CBM) {
-    const int nch = std::min(16 * CELL_CBM, ncols - col0);
+  for (int col0 = 0; col0 < ncols; col0 += 16 * CBM) {
+    const int nch = std::min(16 * CBM, ncols - col0);
     for (int col = 0; col < 8; ++col) {
       const int nc = c->colour_offsets[col + 1] - c->colour_offsets[col];
       if (nc == 0) continue;
       const int64_t nblk = cdiv(nc, 8) * 8 * nparts;
-      const int t = efe_timer_begin(c, EFE_T_CELL);
-      k_cell2<T, RBW><<<nblk, 256, 0, c->stream>>>(
+      const int t = efe_timer_begin(c, CBM == 1 ? EFE_T_CELL_NARROW : EFE_T_CELL);
+      k_cell2<T, RBW, CBM><<<nblk, 256, 0, c->stream>>>(
           nc, nparts, c->d_colour_order + c->colour_offsets[col], c->d_c2g, c->nloc, c->RB, c->KS,
           Ht, Xh + col0, ldh, Y + col0, ldy, c->d_minv, nch);
-      efe_timer_end(c, EFE_T_CELL, t);
+      efe_timer_end(c, CBM == 1 ? EFE_T_CELL_NARROW : EFE_T_CELL, t);
     }
   }
 }
@@ -543,7 +545,8 @@ efe_status efe_apply_H_internal(efe_ctx *c, const double *XC, int64_t ldx, const
   if (c->nproj && (s = efe_ws(c, 1, (size_t)c->nproj * ncols * 8, (void **)&W))) return s;
   const int nf = c->nf;
   double *YE = Y + c->n_nodes * ldy;
-  const int t_apply = efe_timer_begin(c, EFE_T_APPLY);
+  const int t_cls = ncols <= 16 ? EFE_T_APPLY_NARROW : EFE_T_APPLY;
+  const int t_apply = efe_timer_begin(c, t_cls);
   // pre: Xh and Y^C = B^T X^E
   {
     const int t = efe_timer_begin(c, EFE_T_PRE);
@@ -565,10 +568,16 @@ efe_status efe_apply_H_internal(efe_ctx *c, const double *XC, int64_t ldx, const
     }
   }
   // cell GEMM, colour by colour
-  if (prec == EFE_FP64) {
-    launch_cell2<double, 2>(c, c->d_Htile64, Xh, ldh, Y, ldy, ncols);
+  // 160-column register tiles; a single 16-column tile (six row blocks per
+  // wave, one part per cell) for narrow blocks such as the Lanczos vector
+  if (prec == EFE_FP64 && ncols <= 16) {
+    launch_cell2<double, 6, 1>(c, c->d_Htile64, Xh, ldh, Y, ldy, ncols);
+  } else if (prec == EFE_FP64) {
+    launch_cell2<double, 2, 10>(c, c->d_Htile64, Xh, ldh, Y, ldy, ncols);
+  } else if (prec == EFE_FP32 && ncols <= 16) {
+    launch_cell2<float, 6, 1>(c, c->d_Htile32, Xh, ldh, Y, ldy, ncols);
   } else if (prec == EFE_FP32) {
-    launch_cell2<float, 3>(c, c->d_Htile32, Xh, ldh, Y, ldy, ncols);
+    launch_cell2<float, 3, 10>(c, c->d_Htile32, Xh, ldh, Y, ldy, ncols);
   } else {
     const int NT = 32;
     const int ntiles = (int)cdiv(ncols, NT);
@@ -607,7 +616,7 @@ efe_status efe_apply_H_internal(efe_ctx *c, const double *XC, int64_t ldx, const
     }
   }
   efe_timer_end(c, EFE_T_POST, t_post);
-  efe_timer_end(c, EFE_T_APPLY, t_apply);
+  efe_timer_end(c, t_cls, t_apply);
   HIPCHK(c, hipGetLastError());
   return EFE_OK;
 }

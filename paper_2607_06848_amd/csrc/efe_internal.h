@@ -112,8 +112,8 @@ struct efe_ctx {
 
   // event timing (efe_timing)
   bool timing = false;
-  std::vector<hipEvent_t> tev[6];   // start/stop pairs per kernel class
-  int64_t tused[6] = {0, 0, 0, 0, 0, 0};
+  std::vector<hipEvent_t> tev[8];   // start/stop pairs per kernel class
+  int64_t tused[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 };
 
 // ------------------------------------------------------------------ helpers
@@ -203,6 +203,8 @@ efe_status efe_enr_block_inv(efe_ctx *ctx, const double *XE, int64_t ldx, double
 #define EFE_T_RECUR 3    // residual recurrence update
 #define EFE_T_APPLY 4    // a whole H apply
 #define EFE_T_RR 5       // a whole Rayleigh-Ritz
-#define EFE_T_N 6
+#define EFE_T_CELL_NARROW 6    // colour pass of a block of <= 16 vectors
+#define EFE_T_APPLY_NARROW 7   // H apply of a block of <= 16 vectors
+#define EFE_T_N 8
 int efe_timer_begin(efe_ctx *ctx, int which);
 void efe_timer_end(efe_ctx *ctx, int which, int slot);

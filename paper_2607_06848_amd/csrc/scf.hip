@@ -145,30 +145,56 @@ __global__ __launch_bounds__(256) void k_load_vector(int nloc, int nqp, const in
   }
 }
 
-// y += K x on interior nodes for the cells of one colour (shared cell matrix)
-__global__ __launch_bounds__(256) void k_stiff_apply(int ncells, const int32_t *__restrict__ cells,
-                                                     int nloc, const int32_t *__restrict__ c2g,
-                                                     const double *__restrict__ K,
-                                                     const double *__restrict__ x,
-                                                     const double *__restrict__ minv,
-                                                     double *__restrict__ y,
-                                                     const double *__restrict__ done) {
-  __shared__ double xs[EFE_MAXLOC];
-  const int ci = blockIdx.x;
-  if (ci >= ncells || (done && *done != 0.0)) return;
-  const int64_t cell = cells[ci];
-  for (int l = threadIdx.x; l < nloc; l += blockDim.x) {
-    const int32_t node = c2g[cell * nloc + l];
-    xs[l] = minv[node] == 0.0 ? 0.0 : x[node];
+// y += K x over all cells in one launch: eight cells per work-group share
+// every row of the (symmetric, shared) cell stiffness read from memory, read
+// by columns so that consecutive lanes read consecutive entries; results are
+// added to the interior nodes atomically (a node sits in up to eight cells)
+constexpr int STIFF_CPB = 8;
+__global__ __launch_bounds__(256) void k_stiff_apply_all(int64_t ncells, int nloc,
+                                                         const int32_t *__restrict__ c2g,
+                                                         const double *__restrict__ K,
+                                                         const double *__restrict__ x,
+                                                         const double *__restrict__ minv,
+                                                         double *__restrict__ y,
+                                                         const double *__restrict__ done) {
+  __shared__ double xs[STIFF_CPB][EFE_MAXLOC];
+  __shared__ int32_t gs[STIFF_CPB][EFE_MAXLOC];
+  if (done && *done != 0.0) return;
+  const int64_t c0 = (int64_t)blockIdx.x * STIFF_CPB;
+  const int ncb = (int)min<int64_t>(STIFF_CPB, ncells - c0);
+  for (int i = threadIdx.x; i < STIFF_CPB * nloc; i += blockDim.x) {
+    const int cc = i / nloc, l = i % nloc;
+    double v = 0.0;
+    int32_t node = -1;
+    if (cc < ncb) {
+      node = c2g[(c0 + cc) * nloc + l];
+      v = minv[node] == 0.0 ? 0.0 : x[node];
+      if (minv[node] == 0.0) node = -1;
+    }
+    xs[cc][l] = v;
+    gs[cc][l] = node;
   }
   __syncthreads();
-  for (int l = threadIdx.x; l < nloc; l += blockDim.x) {
-    const int32_t node = c2g[cell * nloc + l];
-    if (minv[node] == 0.0) continue;
-    const double *kr = K + (int64_t)l * nloc;
-    double acc = 0.0;
-    for (int m = 0; m < nloc; ++m) acc += kr[m] * xs[m];
-    y[node] += acc;
+  const int t = threadIdx.x;
+  const int l0 = t, l1 = t + 256;
+  double a0[STIFF_CPB], a1[STIFF_CPB];
+#pragma unroll
+  for (int cc = 0; cc < STIFF_CPB; ++cc) a0[cc] = a1[cc] = 0.0;
+  for (int m = 0; m < nloc; ++m) {
+    const double k0 = l0 < nloc ? K[(int64_t)m * nloc + l0] : 0.0;
+    const double k1 = l1 < nloc ? K[(int64_t)m * nloc + l1] : 0.0;
+#pragma unroll
+    for (int cc = 0; cc < STIFF_CPB; ++cc) {
+      const double xv = xs[cc][m];
+      a0[cc] += k0 * xv;
+      a1[cc] += k1 * xv;
+    }
+  }
+#pragma unroll
+  for (int cc = 0; cc < STIFF_CPB; ++cc) {
+    if (cc >= ncb) break;
+    if (l0 < nloc && gs[cc][l0] >= 0) atomicAdd(&y[gs[cc][l0]], a0[cc]);
+    if (l1 < nloc && gs[cc][l1] >= 0) atomicAdd(&y[gs[cc][l1]], a1[cc]);
   }
 }
 
@@ -617,13 +643,8 @@ static efe_status stiff_apply(efe_ctx *c, const double *x, double *y, const doub
     k_cg_zero<<<cdiv(c->n_nodes, 256), 256, 0, c->stream>>>(c->n_nodes, y, sc);
   else
     HIPCHK(c, hipMemsetAsync(y, 0, c->n_nodes * 8, c->stream));
-  for (int col = 0; col < 8; ++col) {
-    const int nc = c->colour_offsets[col + 1] - c->colour_offsets[col];
-    if (!nc) continue;
-    k_stiff_apply<<<nc, 256, 0, c->stream>>>(nc, c->d_colour_order + c->colour_offsets[col],
-                                             c->nloc, c->d_c2g, c->d_K, x, c->d_minv, y,
-                                             sc ? sc + 4 : nullptr);
-  }
+  k_stiff_apply_all<<<cdiv(c->n_cells, STIFF_CPB), 256, 0, c->stream>>>(
+      c->n_cells, c->nloc, c->d_c2g, c->d_K, x, c->d_minv, y, sc ? sc + 4 : nullptr);
   HIPCHK(c, hipGetLastError());
   return EFE_OK;
 }

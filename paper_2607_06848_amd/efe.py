@@ -228,7 +228,8 @@ class Context:
         return torch.zeros((self.rows, ld), dtype=torch.float64, device="cuda")[:, :ncols]
 
     # -------------------------------------------------------------- timing
-    TIMERS = {"cell": 0, "pre": 1, "post": 2, "recur": 3, "apply": 4, "rr": 5}
+    TIMERS = {"cell": 0, "pre": 1, "post": 2, "recur": 3, "apply": 4, "rr": 5,
+              "cell_narrow": 6, "apply_narrow": 7}
 
     def timing(self, enable):
         self._check(lib().efe_timing(self.h, 1 if enable else 0))
