@@ -251,7 +251,8 @@ def main():
         f"({cell_ms / max(ncell_l, 1):.3f} ms avg), RR {rr_ms / max(nrr, 1):.1f} ms, "
         f"recurrence {rec_ms / max(nrec, 1):.3f} ms avg")
     breakdown = {k: float(np.mean([r[k] for r in reps])) for k in
-                 ("t_poisson_ms", "t_filter_ms", "t_rr_ms", "t_density_ms", "t_other_ms")}
+                 ("t_poisson_ms", "t_operators_ms", "t_bound_ms", "t_filter_ms", "t_rr_ms",
+                  "t_density_ms", "t_energy_ms", "t_other_ms")}
     # roofline of the dominant kernel: one colour pass of the cell GEMM
     cells_per_launch = ctx.n_cells / 8.0
     flops_per_launch = 2.0 * ctx.nloc ** 2 * N * cells_per_launch

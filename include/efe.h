@@ -192,7 +192,11 @@ typedef struct {
   double E, F, E_band, E_xc, E_el; /* energies at the output density (Ha)      */
   double mu, n_el, drho, dE;       /* Fermi level, int rho_out, ||rho_out - rho_in||, E - E_prev */
   double max_occ_res, b;           /* largest residual of occupied states, bound */
+  /* wall times (ms): Poisson solve for rho_in; filter passes; Rayleigh-Ritz;
+   * occupied-state density; Anderson mixing; operator rebuild for the new
+   * potential; Lanczos bound; Poisson solve and energy sums at rho_out */
   double t_poisson_ms, t_filter_ms, t_rr_ms, t_density_ms, t_other_ms;
+  double t_operators_ms, t_bound_ms, t_energy_ms;
   int32_t iter, passes, cg_iters;
 } efe_scf_report;
 

@@ -252,49 +252,85 @@ __global__ void k_veff(int64_t n, const double *__restrict__ rho, const double *
   v[i] = phi_at[i] + phiq[i] + vs[i] + vxc;
 }
 
-// Fermi level by bisection (one thread): 2 sum f = Ne; writes mu, f, band, TS
-__global__ void k_fermi(int N, const double *__restrict__ lam, double ne, double kT,
-                        double *__restrict__ f, double *__restrict__ out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double lo = lam[0], hi = lam[0];
-  for (int i = 1; i < N; ++i) {
+// Fermi level by bisection: 2 sum f = Ne; writes mu, f, band, TS.  One
+// work-group of 256 threads; every bisection step sums over the eigenvalues
+// in a fixed tree order, so the result does not depend on timing.
+__device__ __forceinline__ void fermi_reduce3(double *a, double *b, double *cc, double x, double y,
+                                              double z) {
+  const int t = threadIdx.x;
+  a[t] = x;
+  b[t] = y;
+  cc[t] = z;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (t < s) {
+      a[t] += a[t + s];
+      b[t] += b[t + s];
+      cc[t] += cc[t + s];
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void k_fermi(int N, const double *__restrict__ lam, double ne,
+                                               double kT, double *__restrict__ f,
+                                               double *__restrict__ out) {
+  __shared__ double ra[256], rb[256], rc[256];
+  const int t = threadIdx.x;
+  double lo = INFINITY, hi = -INFINITY;
+  for (int i = t; i < N; i += 256) {
     lo = fmin(lo, lam[i]);
     hi = fmax(hi, lam[i]);
   }
-  lo -= 50.0 * kT + 1.0;
-  hi += 50.0 * kT + 1.0;
+  ra[t] = lo;
+  rb[t] = hi;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (t < s) {
+      ra[t] = fmin(ra[t], ra[t + s]);
+      rb[t] = fmax(rb[t], rb[t + s]);
+    }
+    __syncthreads();
+  }
+  lo = ra[0] - (50.0 * kT + 1.0);
+  hi = rb[0] + (50.0 * kT + 1.0);
+  __syncthreads();
   // 2 sum f - N_e as the integer 2 #{lam <= mu} - N_e plus the Fermi tails
   // (f above mu, 1 - f below, each without cancellation), so that the sign
   // stays resolved inside a gap much wider than kT
   for (int it = 0; it < 200; ++it) {
     const double mu = 0.5 * (lo + hi);
-    double up = 0.0, down = 0.0;
-    int nbelow = 0;
-    for (int i = 0; i < N; ++i) {
+    double up = 0.0, down = 0.0, nbelow = 0.0;
+    for (int i = t; i < N; i += 256) {
       const double x = (lam[i] - mu) / kT;
       if (x <= 0.0) {
-        ++nbelow;
+        nbelow += 1.0;
         down += 1.0 / (1.0 + exp(-x));
       } else {
         up += 1.0 / (1.0 + exp(x));
       }
     }
-    const double excess = (2.0 * nbelow - ne) + 2.0 * (up - down);
+    fermi_reduce3(ra, rb, rc, up, down, nbelow);
+    const double excess = (2.0 * rc[0] - ne) + 2.0 * (ra[0] - rb[0]);
     if (excess < 0.0) lo = mu;
     else hi = mu;
+    __syncthreads();
   }
   const double mu = 0.5 * (lo + hi);
   double band = 0.0, ts = 0.0;
-  for (int i = 0; i < N; ++i) {
+  for (int i = t; i < N; i += 256) {
     const double x = (lam[i] - mu) / kT;
     const double fi = x > 0 ? exp(-x) / (1.0 + exp(-x)) : 1.0 / (1.0 + exp(x));
     f[i] = fi;
     band += 2.0 * fi * lam[i];
     if (fi > 0.0 && fi < 1.0) ts += fi * log(fi) + (1.0 - fi) * log(1.0 - fi);
   }
-  out[0] = mu;
-  out[1] = band;
-  out[2] = -2.0 * kT * ts;
+  fermi_reduce3(ra, rb, rc, band, ts, 0.0);
+  if (t == 0) {
+    out[0] = mu;
+    out[1] = ra[0];
+    out[2] = -2.0 * kT * rb[0];
+  }
 }
 
 // rho(q) = 2 sum_j f_j psi_j(q)^2, psi = N3 Xh_cell + sum_I phi_I(q) V^E_I
@@ -770,11 +806,15 @@ extern "C" efe_status efe_scf_step(efe_ctx *c, double *V, int32_t N, int64_t ld,
   k_veff<<<cdiv(nq, T), T, 0, c->stream>>>(nq, s.rho_in, s.phi_at, s.phiq, s.v_short, s.v_in);
   HIPCHK(c, hipStreamSynchronize(c->stream));
   const double t_pois = ms_since(t0);
+  auto tb = std::chrono::steady_clock::now();
   if ((st = efe_build_operators(c, s.v_in, prm->prec == EFE_FP64 ? 0 : (1 << prm->prec)))) return st;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const double t_ops = ms_since(tb);
   // 2. eigen-solve passes
+  tb = std::chrono::steady_clock::now();
   double b;
   if ((st = efe_spectrum_upper_bound(c, v0, prm->lanczos_steps, &b))) return st;
-  auto t1 = std::chrono::steady_clock::now();
+  const double t_bound = ms_since(tb);
   double t_filter = 0.0, t_rr = 0.0;
   double *res;
   if ((st = efe_ws(c, 30, (size_t)N * 8, (void **)&res))) return st;
@@ -804,7 +844,7 @@ extern "C" efe_status efe_scf_step(efe_ctx *c, double *V, int32_t N, int64_t ld,
   if (!s.f && (st = efe_alloc(c, (void **)&s.f, 4096 * 8))) return st;
   if (N > 4096) EFE_FAIL(c, EFE_EINVAL, "more than 4096 vectors");
   double *fo = s.scal + 8;   // mu, band, TS
-  k_fermi<<<1, 1, 0, c->stream>>>(N, lambda, ne, prm->kT, s.f, fo);
+  k_fermi<<<1, 256, 0, c->stream>>>(N, lambda, ne, prm->kT, s.f, fo);
   std::vector<double> fh(N), fermi(3), resh(N);
   HIPCHK(c, hipMemcpyAsync(fh.data(), s.f, N * 8, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipMemcpyAsync(fermi.data(), fo, 3 * 8, hipMemcpyDeviceToHost, c->stream));
@@ -859,6 +899,7 @@ extern "C" efe_status efe_scf_step(efe_ctx *c, double *V, int32_t N, int64_t ld,
   HIPCHK(c, hipStreamSynchronize(c->stream));
   const double t_dens = ms_since(t2);
   // 4. energies at rho_out
+  tb = std::chrono::steady_clock::now();
   HIPCHK(c, hipMemcpyAsync(s.phi_out, s.phi_rem, c->n_nodes * 8, hipMemcpyDeviceToDevice, c->stream));
   if ((st = poisson(c, s.rho_out, s.rho_at, s.phi_out, prm->cg_rtol, prm->cg_maxit, &cg_it2)))
     return st;
@@ -873,6 +914,7 @@ extern "C" efe_status efe_scf_step(efe_ctx *c, double *V, int32_t N, int64_t ld,
   std::vector<double> sh(7);
   HIPCHK(c, hipMemcpyAsync(sh.data(), sums, 7 * 8, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  rep->t_energy_ms = ms_since(tb);
   const double E_el = s.e_const + sh[2] + 0.5 * sh[3] + sh[4];
   const double E = fermi[1] - sh[0] + sh[1] + E_el;
   rep->E = E;
@@ -893,6 +935,8 @@ extern "C" efe_status efe_scf_step(efe_ctx *c, double *V, int32_t N, int64_t ld,
   rep->t_filter_ms = t_filter;
   rep->t_rr_ms = t_rr;
   rep->t_density_ms = t_dens;
+  rep->t_operators_ms = t_ops;
+  rep->t_bound_ms = t_bound;
   s.E_prev = E;
   s.have_E = true;
   // 5. Anderson mixing of rho_in

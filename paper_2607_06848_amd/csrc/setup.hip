@@ -516,39 +516,64 @@ __global__ void k_local_potential(MeshGeo g, const double *__restrict__ xq1, int
   vq[idx] = v;
 }
 
-// Cell Hamiltonian 1/2 K + N^T diag(W v_c) N, written in the operand layout of
-// the 16x16x4 MFMA: tile[cell][rb][ks][lane] = H[16 rb + lane%16][4 ks + lane/16].
-// One block per (cell, 16-row block).
-__global__ __launch_bounds__(256) void k_build_hcell(int nloc, int nqp, int RB, int KS,
+// Cell Hamiltonians H_c = 1/2 K + N^T diag(w v_c) N (Eq. Hcell with the
+// local potential at the Gauss points) on v_mfma_f64_16x16x4.  One work-group
+// per (cell, 16-row block): the block's 16 columns of diag(w v_c) N sit in LDS,
+// and each wave forms 16 x 16 tiles of the transposed product
+// D'[j][i] = sum_q N[q][j] (w v N)[q][16 rb + i], whose accumulator layout
+// (lane l of register v: j = j0 + 4 v + l/16, i = l % 16) is exactly the
+// stored operand layout tile[cell][rb][j/4][i + 16 (j%4)] = base + 16 j + i,
+// so every register is one contiguous 512-byte store.  Quadrature steps past
+// nqp meet zero rows of the LDS strip.
+typedef double v4d_b __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void k_build_hcell(int nloc, int nqp, int RB, int KS, int KQ8,
                                                      const double *__restrict__ N3,
                                                      const double *__restrict__ W3,
                                                      const double *__restrict__ K,
                                                      const double *__restrict__ vq,
                                                      double *__restrict__ H64,
                                                      float *__restrict__ H32) {
-  extern __shared__ double sm[];
-  double *wv = sm;                 // [nqp]
-  double *nr = sm + nqp;           // [nqp][16]  N3[q][16 rb + i]
+  extern __shared__ double bs[];   // [4 KQ8][16]: (w v N)[q][16 rb + i]
   const int cell = blockIdx.x / RB, rb = blockIdx.x % RB;
-  for (int q = threadIdx.x; q < nqp; q += blockDim.x)
-    wv[q] = W3[q] * vq[(int64_t)cell * nqp + q];
-  for (int idx = threadIdx.x; idx < nqp * 16; idx += blockDim.x) {
-    int q = idx / 16, i = idx % 16, row = 16 * rb + i;
-    nr[idx] = row < nloc ? N3[(int64_t)q * nloc + row] : 0.0;
+  for (int idx = threadIdx.x; idx < 64 * KQ8; idx += blockDim.x) {
+    const int q = idx / 16, row = 16 * rb + idx % 16;
+    bs[idx] = (q < nqp && row < nloc)
+                  ? W3[q] * vq[(int64_t)cell * nqp + q] * N3[(int64_t)q * nloc + row]
+                  : 0.0;
   }
   __syncthreads();
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, li = lane % 16, lk = lane / 16;
+  const int JT = (4 * KS + 15) / 16;
   const int64_t tbase = ((int64_t)cell * RB + rb) * KS * 64;
-  for (int idx = threadIdx.x; idx < KS * 64; idx += blockDim.x) {
-    const int ks = idx / 64, lane = idx % 64;
-    const int i = lane % 16, j = 4 * ks + lane / 16, row = 16 * rb + i;
-    double h = 0.0;
-    if (row < nloc && j < nloc) {
-      double acc = 0.0;
-      for (int q = 0; q < nqp; ++q) acc += nr[q * 16 + i] * wv[q] * N3[(int64_t)q * nloc + j];
-      h = 0.5 * K[(int64_t)row * nloc + j] + acc;
+  for (int jt = wave; jt < JT; jt += 4) {
+    const int j0 = 16 * jt;
+    const double *np = N3 + min(j0 + li, nloc - 1);
+    v4d_b acc = {0.0, 0.0, 0.0, 0.0};
+    double a[8], na[8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) a[s] = np[(int64_t)min(4 * s + lk, nqp - 1) * nloc];
+    for (int k0 = 0; k0 < KQ8; k0 += 8) {
+      // next batch of N^T fragments (clamped rows; they meet zero LDS rows)
+#pragma unroll
+      for (int s = 0; s < 8; ++s)
+        na[s] = np[(int64_t)min(4 * (k0 + 8 + s) + lk, nqp - 1) * nloc];
+#pragma unroll
+      for (int s = 0; s < 8; ++s)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], bs[(4 * (k0 + s) + lk) * 16 + li], acc,
+                                                   0, 0, 0);
+#pragma unroll
+      for (int s = 0; s < 8; ++s) a[s] = na[s];
     }
-    H64[tbase + idx] = h;
-    if (H32) H32[tbase + idx] = (float)h;
+    const int row = 16 * rb + li;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int j = j0 + 4 * v + lk;
+      if (j >= 4 * KS) continue;
+      const double h =
+          (row < nloc && j < nloc) ? 0.5 * K[(int64_t)row * nloc + j] + acc[v] : 0.0;
+      H64[tbase + 16 * j + li] = h;
+      if (H32) H32[tbase + 16 * j + li] = (float)h;
+    }
   }
 }
 
@@ -732,9 +757,11 @@ efe_status efe_build_operators(efe_ctx *c, const double *vq, int precisions) {
   if (want32 && !c->d_Htile32 && (s = efe_alloc(c, (void **)&c->d_Htile32, tiles * 4))) return s;
   const int64_t tiles16 = c->n_cells * c->RB * c->KS32 * 64 * 8;
   if (want16 && !c->d_Htile16 && (s = efe_alloc(c, (void **)&c->d_Htile16, tiles16 * 2))) return s;
-  const size_t shm = (size_t)c->nqp * 17 * 8;
+  const int KQ8 = (int)cdiv(cdiv(c->nqp, 4), 8) * 8;   // quadrature k steps, padded
+  const size_t shm = (size_t)KQ8 * 64 * 8;
+  if (shm > 64 * 1024) EFE_FAIL(c, EFE_EINVAL, "too many Gauss points per cell");
   k_build_hcell<<<c->n_cells * c->RB, 256, shm, c->stream>>>(
-      c->nloc, c->nqp, c->RB, c->KS, c->d_N3, c->d_W3, c->d_K, c->d_vq, c->d_Htile64,
+      c->nloc, c->nqp, c->RB, c->KS, KQ8, c->d_N3, c->d_W3, c->d_K, c->d_vq, c->d_Htile64,
       want32 ? c->d_Htile32 : nullptr);
   if (want16)
     k_tile_bf16<<<cdiv(tiles16, 256), 256, 0, c->stream>>>(c->n_cells, c->RB, c->KS, c->KS32,

@@ -60,7 +60,8 @@ PROGRESS = ctypes.CFUNCTYPE(None, ctypes.c_int32, ctypes.c_double, ctypes.c_doub
 class ScfReport(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in
                 ("E", "F", "E_band", "E_xc", "E_el", "mu", "n_el", "drho", "dE", "max_occ_res",
-                 "b", "t_poisson_ms", "t_filter_ms", "t_rr_ms", "t_density_ms", "t_other_ms")] + \
+                 "b", "t_poisson_ms", "t_filter_ms", "t_rr_ms", "t_density_ms", "t_other_ms",
+                 "t_operators_ms", "t_bound_ms", "t_energy_ms")] + \
                [("iter", ctypes.c_int32), ("passes", ctypes.c_int32), ("cg_iters", ctypes.c_int32)]
 
     def as_dict(self):
