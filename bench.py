@@ -30,7 +30,7 @@ sys.path.insert(0, ROOT)
 
 PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15, "hbm": 8.0e12}
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
-CELL_KERNEL = {"fp64": "k_cell2<double, 2, 10>", "fp32": "k_cell2<float, 3, 10>",
+CELL_KERNEL = {"fp64": "k_cell2<double, 1, 10>", "fp32": "k_cell2<float, 1, 10>",
                "bf16": "k_cell_bf16<32>"}
 
 
@@ -233,7 +233,8 @@ def main():
     t0 = time.perf_counter()
     for i in range(args.steps):
         reps.append(ctx.scf_step(V, lam, v0, deg, **kw))
-        log(f"step {i}: E {reps[-1]['E']:.8f} dE {reps[-1]['dE']:.2e}")
+        log(f"step {i}: E {reps[-1]['E']:.8f} dE {reps[-1]['dE']:.2e} CG iterations "
+            f"{reps[-1]['cg_iters']}")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ncell_l, cell_ms = ctx.timing_get("cell")

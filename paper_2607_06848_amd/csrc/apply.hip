@@ -17,6 +17,14 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // columns per lane (x 64) of the row-reduction kernels
 constexpr int POST_Q = 3;
 
+// value of v in lane l (l wave-uniform), for every lane: two readlanes
+__device__ inline double lane_bcast(double v, int l) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(unsigned)(u & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(u >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 // block index of the calling work-group under an XcdSplit, or -1
 __device__ inline int64_t xcd_block(const XcdSplit &x) {
   const int xcd = blockIdx.x % 8;
@@ -62,7 +70,10 @@ __global__ __launch_bounds__(256) void k_pre(int64_t n_nodes, int ncols, const d
       const int col = c0 + 64 * q + lane;
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
-        xh[q][j] = (inner[j] && col < ncols) ? s[j] * XC[(n0 + j) * ldx + col] : 0.0;
+        // unconditional loads at clamped addresses keep every load of the
+        // group in flight at once; the select drops what they brought in
+        const double xv = XC[(n0 + min(j, nn - 1)) * ldx + min(col, ncols - 1)];
+        xh[q][j] = (inner[j] && col < ncols) ? s[j] * xv : 0.0;
         y[q][j] = 0.0;
       }
     }
@@ -74,7 +85,7 @@ __global__ __launch_bounds__(256) void k_pre(int64_t n_nodes, int ncols, const d
 #pragma unroll
         for (int q = 0; q < PRE_Q; ++q) {
           const int col = c0 + 64 * q + lane;
-          v[q] = col < ncols ? xe[(int64_t)k * lde + col] : 0.0;
+          v[q] = xe[(int64_t)k * lde + min(col, ncols - 1)];
         }
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
@@ -138,8 +149,15 @@ struct CellMfma<float> {
   __device__ static inline int row(int v, int lk) { return 4 * lk + v; }
 };
 
+// waves per SIMD the wide tiles are compiled for: the FP64 accumulators of
+// one row block x ten column blocks leave room for three, the FP32 ones for four
+template <typename T, int CBM>
+constexpr int cell_waves() {
+  return CBM == 1 ? 1 : (sizeof(T) == 8 ? 3 : 4);
+}
+
 template <typename T, int RBW, int CBM>
-__global__ __launch_bounds__(256) void k_cell2(int ncells, int nparts,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(cell_waves<T, CBM>()))) void k_cell2(int ncells, int nparts,
                                                const int32_t *__restrict__ cells,
                                                const int32_t *__restrict__ c2g, int nloc, int RB,
                                                int KS, const T *__restrict__ Ht,
@@ -179,19 +197,38 @@ __global__ __launch_bounds__(256) void k_cell2(int ncells, int nparts,
   // Out-of-range X rows and columns are zeroed when they are written to LDS;
   // a clamped A fragment then multiplies zero rows of Xs (k past the end) or
   // feeds accumulators that are never stored (row blocks past the end).
-  double xr[EPT];
+  // wide tiles read the gathered rows as pairs of doubles (ldx even, so the
+  // pairs never cross a row) with 32-bit element offsets (the host checks
+  // n_nodes * ldx < 2^31)
+  constexpr bool PAIRS = NC >= 32;
+  constexpr int NP = PAIRS ? NC / 2 : NC, EPT2 = PAIRS ? KC * NP / 256 : EPT;
+  static_assert(KC * NP % 256 == 0, "the gather must cover the chunk exactly");
+  const int NPV = (ncols + 1) / 2;
+  double2 xr[EPT2];
   auto stage_load = [&](int ch) {
 #pragma unroll
-    for (int j = 0; j < EPT; ++j) {
-      const int idx = t + 256 * j, r = idx / NC, cc = idx % NC, k = ch * KC + r;
-      xr[j] = Xh[(int64_t)gs[min(k, nloc - 1)] * ldx + min(cc, ncols - 1)];
+    for (int j = 0; j < EPT2; ++j) {
+      const int idx = t + 256 * j, r = idx / NP, cp = idx % NP, k = ch * KC + r;
+      if constexpr (PAIRS) {
+        const uint32_t off = (uint32_t)gs[min(k, nloc - 1)] * (uint32_t)ldx +
+                             2u * (uint32_t)min(cp, NPV - 1);
+        xr[j] = *reinterpret_cast<const double2 *>(Xh + off);
+      } else {
+        xr[j].x = Xh[(int64_t)gs[min(k, nloc - 1)] * ldx + min(cp, ncols - 1)];
+      }
     }
   };
   auto stage_store = [&](int buf, int ch) {
 #pragma unroll
-    for (int j = 0; j < EPT; ++j) {
-      const int idx = t + 256 * j, r = idx / NC, cc = idx % NC, k = ch * KC + r;
-      Xs[buf][r][cc] = (k < nloc && cc < ncols) ? (T)xr[j] : (T)0;
+    for (int j = 0; j < EPT2; ++j) {
+      const int idx = t + 256 * j, r = idx / NP, cp = idx % NP, k = ch * KC + r;
+      const bool kr = k < nloc;
+      if constexpr (PAIRS) {
+        Xs[buf][r][2 * cp] = (kr && 2 * cp < ncols) ? (T)xr[j].x : (T)0;
+        Xs[buf][r][2 * cp + 1] = (kr && 2 * cp + 1 < ncols) ? (T)xr[j].y : (T)0;
+      } else {
+        Xs[buf][r][cp] = (kr && cp < ncols) ? (T)xr[j].x : (T)0;
+      }
     }
   };
   auto a_load = [&](int ch, T (&dst)[4][RBW]) {
@@ -372,18 +409,26 @@ __global__ __launch_bounds__(256) void k_kb_project(int ncols, const int32_t *__
     }
 }
 
-// W[I] = D_I sum_f P^phi_If XE_f (first term of the projector coefficients)
-__global__ __launch_bounds__(256) void k_kb_w_pphi(int nproj, int ncols, int64_t n_enr,
-                                                 const double *__restrict__ Pphi,
-                                                 const double *__restrict__ XE, int64_t lde,
-                                                 const double *__restrict__ D,
-                                                 double *__restrict__ W) {
-  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)nproj * ncols) return;
-  const int I = (int)(idx / ncols), col = (int)(idx % ncols);
+// W[I] = D_I sum_f P^phi_If XE_f (first term of the projector coefficients):
+// one work-group per (projector, 64 columns); the four waves take every
+// fourth f and their sums meet in LDS in a fixed order
+__global__ __launch_bounds__(256) void k_kb_w_pphi(int ncols, int64_t n_enr,
+                                                   const double *__restrict__ Pphi,
+                                                   const double *__restrict__ XE, int64_t lde,
+                                                   const double *__restrict__ D,
+                                                   double *__restrict__ W) {
+  __shared__ double red[4][64];
+  const int I = blockIdx.x;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int col = blockIdx.y * 64 + lane;
+  const int cc = min(col, ncols - 1);
+  const double *p = Pphi + (int64_t)I * n_enr;
   double acc = 0.0;
-  for (int64_t f = 0; f < n_enr; ++f) acc += Pphi[(int64_t)I * n_enr + f] * XE[f * lde + col];
-  W[idx] = D[I] * acc;
+  for (int64_t f = wave; f < n_enr; f += 4) acc += p[f] * XE[f * lde + cc];
+  red[wave][lane] = acc;
+  __syncthreads();
+  if (wave == 0 && col < ncols)
+    W[(int64_t)I * ncols + col] = D[I] * (((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane]);
 }
 
 // Y^C[node] += sum_e P^C_e W[atom_e] over the node's projector entries; one
@@ -446,21 +491,39 @@ __global__ __launch_bounds__(256) void k_enr_post(int nf, int ncols,
   for (int q = 0; q < POST_Q; ++q)
 #pragma unroll
     for (int k = 0; k < 9; ++k) acc[q][k] = 0.0;
-  for (int32_t s = s0 + wave; s < s1; s += 4) {
-    const int64_t node = snode[s];
-    const double *bb = B_am + (int64_t)s * nf, *cc = C_am + (int64_t)s * nf;
-    double xh[POST_Q], y[POST_Q];
+  // This wave takes support entries s0 + wave + 4 i.  Their node numbers
+  // come in 64 at a time by one vector load, and the 2 nf coefficients of an
+  // entry by one vector load (lane k: B_k, lane 16 + k: C_k) one entry ahead
+  // of their use; readlane hands both to the wave.  Columns are clamped, so
+  // every load is unconditional; the sums of clamped columns are not stored.
+  const int kl = lane & 15;
+  const double *csrc = lane < 16 ? B_am : C_am;
+  auto cload = [&](int32_t s) -> double {
+    return csrc[(int64_t)min(s, s1 - 1) * nf + min(kl, nf - 1)];
+  };
+  for (int32_t sb = s0 + wave; sb < s1; sb += 256) {
+    const int cnt = min(64, (s1 - sb + 3) / 4);
+    const int32_t nodes = snode[min(sb + 4 * lane, s1 - 1)];
+    double cv = cload(sb);
+    for (int i = 0; i < cnt; ++i) {
+      const int32_t s = sb + 4 * i;
+      const int64_t node = __builtin_amdgcn_readlane(nodes, i);
+      const double cn = cload(s + 4);
+      double xh[POST_Q], y[POST_Q];
 #pragma unroll
-    for (int q = 0; q < POST_Q; ++q) {
-      const int col = c0 + 64 * q + lane;
-      xh[q] = col < ncols ? Xh[node * ldh + col] : 0.0;
-      y[q] = col < ncols ? Y[node * ldy + col] : 0.0;
-    }
+      for (int q = 0; q < POST_Q; ++q) {
+        const int col = min(c0 + 64 * q + lane, ncols - 1);
+        xh[q] = Xh[node * ldh + col];
+        y[q] = Y[node * ldy + col];
+      }
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      const double b = k < nf ? bb[k] : 0.0, c = k < nf ? cc[k] : 0.0;
+      for (int k = 0; k < 9; ++k) {
+        const double b = k < nf ? lane_bcast(cv, k) : 0.0;
+        const double c = k < nf ? lane_bcast(cv, 16 + k) : 0.0;
 #pragma unroll
-      for (int q = 0; q < POST_Q; ++q) acc[q][k] += b * xh[q] - c * y[q];
+        for (int q = 0; q < POST_Q; ++q) acc[q][k] += b * xh[q] - c * y[q];
+      }
+      cv = cn;
     }
   }
   if (wave > 0)
@@ -481,6 +544,110 @@ __global__ __launch_bounds__(256) void k_enr_post(int nf, int ncols,
         if (k < nf) atomicAdd(&YE[(int64_t)(I * nf + k) * lde + col], v);
       }
     }
+  }
+}
+
+// ------------------------------------------------------------- one column
+// Single-vector forms of the four row kernels (the Lanczos bound applies
+// H^E to one vector): threads run over nodes or support entries instead of
+// columns, so no lane idles.  Same sums, same order within each node.
+
+// sum of x over the work-group (256 threads), in a fixed order
+__device__ inline double block_sum256(double x, double *red) {
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+  if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = x;
+  __syncthreads();
+  const double t = (red[0] + red[1]) + (red[2] + red[3]);
+  __syncthreads();
+  return t;
+}
+
+__global__ __launch_bounds__(256) void k_pre1(int64_t n_nodes, const double *__restrict__ XC,
+                                              int64_t ldx, const double *__restrict__ scale,
+                                              const double *__restrict__ minv,
+                                              const double *__restrict__ XE, int64_t lde,
+                                              const int32_t *__restrict__ g_ptr,
+                                              const int32_t *__restrict__ g_atom,
+                                              const double *__restrict__ Cg,
+                                              const double *__restrict__ Bg, int nf,
+                                              double *__restrict__ Xh, int64_t ldh, double *Y,
+                                              int64_t ldy) {
+  const int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (n >= n_nodes) return;
+  const int64_t grp = n / 8;
+  const int j = (int)(n % 8);
+  const bool inner = minv[n] != 0.0;
+  double xh = inner ? (scale ? scale[n] : 1.0) * XC[n * ldx] : 0.0, y = 0.0;
+  for (int32_t a = g_ptr[grp]; a < g_ptr[grp + 1]; ++a) {
+    const double *xe = XE + (int64_t)g_atom[a] * nf * lde;
+    for (int k = 0; k < nf; ++k) {
+      const double v = xe[(int64_t)k * lde];
+      xh -= Cg[((int64_t)a * nf + k) * 8 + j] * v;
+      y += Bg[((int64_t)a * nf + k) * 8 + j] * v;
+    }
+  }
+  Xh[n * ldh] = inner ? xh : 0.0;
+  if (Y) Y[n * ldy] = inner ? y : 0.0;
+}
+
+// W[I] += D_I sum_s P^C_s Xh[node_s] over one work item, threads over entries
+__global__ __launch_bounds__(256) void k_kb_project1(const int32_t *__restrict__ items,
+                                                     const int32_t *__restrict__ kbnode,
+                                                     const double *__restrict__ Pc,
+                                                     const double *__restrict__ Xh, int64_t ldh,
+                                                     const double *__restrict__ D,
+                                                     double *__restrict__ W) {
+  __shared__ double red[4];
+  const int32_t *it = items + 3 * (int64_t)blockIdx.x;
+  const int I = it[0];
+  double acc = 0.0;
+  for (int32_t s = it[1] + threadIdx.x; s < it[2]; s += 256) acc += Pc[s] * Xh[(int64_t)kbnode[s] * ldh];
+  const double t = block_sum256(acc, red);
+  if (threadIdx.x == 0) atomicAdd(&W[I], D[I] * t);
+}
+
+// Y^C[node] += sum_e P^C_e W[atom_e], one thread per node
+__global__ __launch_bounds__(256) void k_kb_expand1(int64_t n_nodes,
+                                                    const int32_t *__restrict__ kbnm_ptr,
+                                                    const int32_t *__restrict__ kbnm_atom,
+                                                    const double *__restrict__ Pc_nm,
+                                                    const double *__restrict__ W,
+                                                    double *__restrict__ Y, int64_t ldy) {
+  const int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (n >= n_nodes) return;
+  const int32_t e0 = kbnm_ptr[n], e1 = kbnm_ptr[n + 1];
+  if (e0 == e1) return;
+  double acc = 0.0;
+  for (int32_t e = e0; e < e1; ++e) acc += Pc_nm[e] * W[kbnm_atom[e]];
+  Y[n * ldy] += acc;
+}
+
+// Y^E[I] += sum_s (B_s Xh[node_s] - C_s Y[node_s]) over one work item, threads
+// over entries, one work-group sum per enrichment function
+__global__ __launch_bounds__(256) void k_enr_post1(int nf, const int32_t *__restrict__ items,
+                                                   const int32_t *__restrict__ snode,
+                                                   const double *__restrict__ B_am,
+                                                   const double *__restrict__ C_am,
+                                                   const double *__restrict__ Xh, int64_t ldh,
+                                                   const double *__restrict__ Y, int64_t ldy,
+                                                   double *__restrict__ YE, int64_t lde) {
+  __shared__ double red[4];
+  const int32_t *it = items + 3 * (int64_t)blockIdx.x;
+  const int I = it[0];
+  const int32_t s0 = it[1], s1 = it[2];
+  double acc[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) acc[k] = 0.0;
+  for (int32_t s = s0 + threadIdx.x; s < s1; s += 256) {
+    const int64_t node = snode[s];
+    const double x = Xh[node * ldh], y = Y[node * ldy];
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+      if (k < nf) acc[k] += B_am[(int64_t)s * nf + k] * x - C_am[(int64_t)s * nf + k] * y;
+  }
+  for (int k = 0; k < nf; ++k) {
+    const double t = block_sum256(acc[k], red);
+    if (threadIdx.x == 0) atomicAdd(&YE[(int64_t)(I * nf + k) * lde], t);
   }
 }
 
@@ -540,7 +707,11 @@ efe_status efe_apply_H_internal(efe_ctx *c, const double *XC, int64_t ldx, const
     EFE_FAIL(c, EFE_ESTATE, "reduced-precision cell matrices were not built by efe_set_potential");
   efe_status s;
   double *Xh, *W = nullptr;
-  const int64_t ldh = ncols;
+  // even row length: the cell GEMM reads X^ in pairs of doubles
+  const int64_t ldh = (ncols + 1) & ~1;
+  if (c->nf > 16) EFE_FAIL(c, EFE_EINVAL, "more than 16 enrichment functions per atom");
+  if (c->n_nodes * ldh >= (1ll << 31))
+    EFE_FAIL(c, EFE_EINVAL, "n_nodes x columns exceeds the 32-bit offsets of the cell GEMM");
   if ((s = efe_ws(c, 0, (size_t)c->n_nodes * ldh * 8, (void **)&Xh))) return s;
   if (c->nproj && (s = efe_ws(c, 1, (size_t)c->nproj * ncols * 8, (void **)&W))) return s;
   const int nf = c->nf;
@@ -550,21 +721,31 @@ efe_status efe_apply_H_internal(efe_ctx *c, const double *XC, int64_t ldx, const
   // pre: Xh and Y^C = B^T X^E
   {
     const int t = efe_timer_begin(c, EFE_T_PRE);
-    k_pre<<<cdiv(c->n_nodes, 32), 256, 0, c->stream>>>(c->n_nodes, ncols, XC, ldx, scale,
-                                                       c->d_minv, XE, lde, c->d_g_ptr, c->d_g_atom,
-                                                       c->d_Cg, c->d_Bg, nf, Xh, ldh, Y, ldy);
+    if (ncols == 1)
+      k_pre1<<<cdiv(c->n_nodes, 256), 256, 0, c->stream>>>(c->n_nodes, XC, ldx, scale, c->d_minv,
+                                                           XE, lde, c->d_g_ptr, c->d_g_atom,
+                                                           c->d_Cg, c->d_Bg, nf, Xh, ldh, Y, ldy);
+    else
+      k_pre<<<cdiv(c->n_nodes, 32), 256, 0, c->stream>>>(c->n_nodes, ncols, XC, ldx, scale,
+                                                         c->d_minv, XE, lde, c->d_g_ptr,
+                                                         c->d_g_atom, c->d_Cg, c->d_Bg, nf, Xh, ldh,
+                                                         Y, ldy);
     efe_timer_end(c, EFE_T_PRE, t);
   }
   // projector coefficients
   if (c->nproj) {
-    k_kb_w_pphi<<<cdiv((int64_t)c->nproj * ncols, 256), 256, 0, c->stream>>>(
-        c->nproj, ncols, c->n_enr, c->d_Pphi, XE, lde, c->d_D, W);
+    k_kb_w_pphi<<<dim3(c->nproj, cdiv(ncols, 64)), 256, 0, c->stream>>>(ncols, c->n_enr, c->d_Pphi,
+                                                                        XE, lde, c->d_D, W);
     if (c->n_kb_items) {
       XcdSplit xs;
       for (int i = 0; i <= 8; ++i) xs.off[i] = c->kb_items_off[i];
       dim3 grd(8 * xs.max_len(), cdiv(ncols, 64 * POST_Q));
-      k_kb_project<<<grd, 256, 0, c->stream>>>(ncols, c->d_kb_items, xs, c->d_kbnode, c->d_Pc_am,
-                                               Xh, ldh, c->d_D, W);
+      if (ncols == 1)
+        k_kb_project1<<<c->n_kb_items, 256, 0, c->stream>>>(c->d_kb_items, c->d_kbnode, c->d_Pc_am,
+                                                            Xh, ldh, c->d_D, W);
+      else
+        k_kb_project<<<grd, 256, 0, c->stream>>>(ncols, c->d_kb_items, xs, c->d_kbnode,
+                                                 c->d_Pc_am, Xh, ldh, c->d_D, W);
     }
   }
   // cell GEMM, colour by colour
@@ -573,11 +754,11 @@ efe_status efe_apply_H_internal(efe_ctx *c, const double *XC, int64_t ldx, const
   if (prec == EFE_FP64 && ncols <= 16) {
     launch_cell2<double, 6, 1>(c, c->d_Htile64, Xh, ldh, Y, ldy, ncols);
   } else if (prec == EFE_FP64) {
-    launch_cell2<double, 2, 10>(c, c->d_Htile64, Xh, ldh, Y, ldy, ncols);
+    launch_cell2<double, 1, 10>(c, c->d_Htile64, Xh, ldh, Y, ldy, ncols);
   } else if (prec == EFE_FP32 && ncols <= 16) {
     launch_cell2<float, 6, 1>(c, c->d_Htile32, Xh, ldh, Y, ldy, ncols);
   } else if (prec == EFE_FP32) {
-    launch_cell2<float, 3, 10>(c, c->d_Htile32, Xh, ldh, Y, ldy, ncols);
+    launch_cell2<float, 1, 10>(c, c->d_Htile32, Xh, ldh, Y, ldy, ncols);
   } else {
     const int NT = 32;
     const int ntiles = (int)cdiv(ncols, NT);
@@ -594,8 +775,13 @@ efe_status efe_apply_H_internal(efe_ctx *c, const double *XC, int64_t ldx, const
     }
   }
   if (c->nproj) {
-    k_kb_expand<<<cdiv(c->n_nodes, 4), 256, 0, c->stream>>>(c->n_nodes, ncols, c->d_kbnm_ptr,
-                                                            c->d_kbnm_atom, c->d_Pc_nm, W, Y, ldy);
+    if (ncols == 1)
+      k_kb_expand1<<<cdiv(c->n_nodes, 256), 256, 0, c->stream>>>(c->n_nodes, c->d_kbnm_ptr,
+                                                                 c->d_kbnm_atom, c->d_Pc_nm, W, Y,
+                                                                 ldy);
+    else
+      k_kb_expand<<<cdiv(c->n_nodes, 4), 256, 0, c->stream>>>(c->n_nodes, ncols, c->d_kbnm_ptr,
+                                                              c->d_kbnm_atom, c->d_Pc_nm, W, Y, ldy);
   }
   // enrichment rows
   const int t_post = efe_timer_begin(c, EFE_T_POST);
@@ -611,8 +797,13 @@ efe_status efe_apply_H_internal(efe_ctx *c, const double *XC, int64_t ldx, const
       XcdSplit xs;
       for (int i = 0; i <= 8; ++i) xs.off[i] = c->enr_items_off[i];
       dim3 grd(8 * xs.max_len(), cdiv(ncols, 64 * POST_Q));
-      k_enr_post<<<grd, 256, 0, c->stream>>>(nf, ncols, c->d_enr_items, xs, c->d_snode, c->d_B_am,
-                                             c->d_C_am, Xh, ldh, Y, ldy, YE, ldy);
+      if (ncols == 1)
+        k_enr_post1<<<c->n_enr_items, 256, 0, c->stream>>>(nf, c->d_enr_items, c->d_snode,
+                                                           c->d_B_am, c->d_C_am, Xh, ldh, Y, ldy,
+                                                           YE, ldy);
+      else
+        k_enr_post<<<grd, 256, 0, c->stream>>>(nf, ncols, c->d_enr_items, xs, c->d_snode,
+                                               c->d_B_am, c->d_C_am, Xh, ldh, Y, ldy, YE, ldy);
     }
   }
   efe_timer_end(c, EFE_T_POST, t_post);

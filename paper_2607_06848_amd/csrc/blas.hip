@@ -1,6 +1,9 @@
-// Small FP64 dense kernels used around the hot path: a tiled GEMM for the
-// enrichment blocks and subspace rotations, and a split-K Gram kernel for the
-// tall-skinny V^T M V / V^T H V products of Rayleigh-Ritz.
+// FP64 dense products around the hot path: plain GEMMs (enrichment blocks,
+// subspace rotations) go to rocBLAS; a tiled kernel covers the weighted
+// products, and a split-K kernel the tall-skinny weighted Grams V^T M V of
+// Rayleigh-Ritz.
+#include <rocblas/rocblas.h>
+
 #include "efe_internal.h"
 
 // C = alpha op(A) op(B) (+ beta C), row-major, 64x64 tiles, 16-deep k steps;
@@ -79,6 +82,22 @@ efe_status efe_gemm(efe_ctx *ctx, bool ta, bool tb, int64_t M, int64_t N, int64_
   if (M <= 0 || N <= 0) return EFE_OK;
   if (K <= 0) {
     EFE_FAIL(ctx, EFE_EINVAL, "efe_gemm with K = 0");
+  }
+  if (!wK && M < (1ll << 31) && N < (1ll << 31) && K < (1ll << 31) && lda < (1ll << 31) &&
+      ldb < (1ll << 31) && ldc < (1ll << 31)) {
+    // plain products go to rocBLAS (FP64 MFMA) on the context's stream.  The
+    // row-major C = op(A) op(B) is the column-major C^T = op(B)^T op(A)^T, so
+    // the operands swap and each keeps its own transpose flag.
+    void *hv;
+    efe_status s;
+    if ((s = efe_blas_handle(ctx, &hv))) return s;
+    const rocblas_status st = rocblas_dgemm(
+        (rocblas_handle)hv, tb ? rocblas_operation_transpose : rocblas_operation_none,
+        ta ? rocblas_operation_transpose : rocblas_operation_none, (rocblas_int)N, (rocblas_int)M,
+        (rocblas_int)K, &alpha, B, (rocblas_int)ldb, A, (rocblas_int)lda, &beta, C,
+        (rocblas_int)ldc);
+    if (st != rocblas_status_success) EFE_FAIL(ctx, EFE_EHIP, "rocblas_dgemm failed");
+    return EFE_OK;
   }
   dim3 grid(cdiv(N, 64), cdiv(M, 64), 1);
   if (grid.y > 65535u * 32u) EFE_FAIL(ctx, EFE_EINVAL, "gemm grid too large");

@@ -103,7 +103,9 @@ extern "C" efe_status efe_rayleigh_ritz(efe_ctx *c, double *V, int32_t N, int64_
                                   EFE_FP64)))
       return s;
   }
-  // S = V^T M V, Hp = V^T W
+  // S = V^T M V, Hp = V^T W: tall-skinny products (N x N from all rows) by
+  // the split-K Gram kernel; a library GEMM without split-K leaves most of
+  // the chip idle at this shape
   HIPCHK(c, hipMemsetAsync(S, 0, (size_t)2 * N * N * 8, c->stream));
   if ((s = efe_gram(c, N, N, nn, 1.0, V, ld, V, ld, c->d_m_int, S, N))) return s;
   if (ne) {

@@ -25,6 +25,8 @@ struct ScfState {
   double *phi_rem = nullptr, *phi_out = nullptr;                      // [n_nodes]
   double *Kdiag = nullptr;                                            // [n_nodes]
   double *cg = nullptr;                                               // r, z, p, Ap, b
+  double *Ktile = nullptr;   // cell stiffness in the 16x16x4 MFMA operand layout
+  double *part = nullptr;    // per-work-group partial sums of the CG reductions
   double *hist = nullptr;                                             // Anderson X, F ring
   double *scal = nullptr;                                             // device scalars
   double *f = nullptr;                                                // occupations [N]
@@ -46,7 +48,7 @@ void efe_scf_free(efe_ctx *c) {
   ScfState &s = *(ScfState *)c->scf;
   void *ptrs[] = {s.rho_at, s.phi_at, s.v_short, s.rho_in, s.rho_out, s.v_in, s.phiq,
                   s.phi_rem, s.phi_out, s.Kdiag, s.cg, s.hist, s.scal, s.f, s.cell_ptr,
-                  s.cell_atom};
+                  s.cell_atom, s.Ktile, s.part};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   delete (ScfState *)c->scf;
@@ -145,56 +147,75 @@ __global__ __launch_bounds__(256) void k_load_vector(int nloc, int nqp, const in
   }
 }
 
-// y += K x over all cells in one launch: eight cells per work-group share
-// every row of the (symmetric, shared) cell stiffness read from memory, read
-// by columns so that consecutive lanes read consecutive entries; results are
-// added to the interior nodes atomically (a node sits in up to eight cells)
-constexpr int STIFF_CPB = 8;
-__global__ __launch_bounds__(256) void k_stiff_apply_all(int64_t ncells, int nloc,
+typedef double v4d_s __attribute__((ext_vector_type(4)));
+
+// Cell stiffness in the operand layout of v_mfma_f64_16x16x4:
+// Kt[rb][ks][lane] = K[16 rb + lane%16][4 ks + lane/16] (zero past nloc)
+__global__ void k_tile_K(int nloc, int RB, int KS, const double *__restrict__ K,
+                         double *__restrict__ Kt) {
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)RB * KS * 64) return;
+  const int l = (int)(idx % 64);
+  const int ks = (int)((idx / 64) % KS), rb = (int)(idx / (64 * (int64_t)KS));
+  const int row = 16 * rb + l % 16, col = 4 * ks + l / 16;
+  Kt[idx] = (row < nloc && col < nloc) ? K[(int64_t)row * nloc + col] : 0.0;
+}
+
+// y += K x over all cells in one launch, on FP64 MFMA: a work-group takes 16
+// cells, whose gathered x form the 16 columns of the B operand (in LDS,
+// zero on boundary nodes and past nloc), and four row blocks of the shared
+// cell stiffness (A operand, MFMA layout), one per wave; the results go to
+// the interior nodes atomically (a node sits in up to 8 cells).
+constexpr int STIFF_CELLS = 16;
+__global__ __launch_bounds__(256) void k_stiff_apply_all(int64_t ncells, int nloc, int RB, int KS,
                                                          const int32_t *__restrict__ c2g,
-                                                         const double *__restrict__ K,
+                                                         const double *__restrict__ Kt,
                                                          const double *__restrict__ x,
                                                          const double *__restrict__ minv,
                                                          double *__restrict__ y,
                                                          const double *__restrict__ done) {
-  __shared__ double xs[STIFF_CPB][EFE_MAXLOC];
-  __shared__ int32_t gs[STIFF_CPB][EFE_MAXLOC];
+  extern __shared__ double xs[];   // [STIFF_CELLS][4 KS + 1]
   if (done && *done != 0.0) return;
-  const int64_t c0 = (int64_t)blockIdx.x * STIFF_CPB;
-  const int ncb = (int)min<int64_t>(STIFF_CPB, ncells - c0);
-  for (int i = threadIdx.x; i < STIFF_CPB * nloc; i += blockDim.x) {
-    const int cc = i / nloc, l = i % nloc;
+  const int KP1 = 4 * KS + 1;      // odd row stride: the 16 cells hit different banks
+  const int64_t c0 = (int64_t)blockIdx.x * STIFF_CELLS;
+  const int ncb = (int)min<int64_t>(STIFF_CELLS, ncells - c0);
+  for (int i = threadIdx.x; i < STIFF_CELLS * KP1; i += blockDim.x) {
+    const int cc = i / KP1, l = i % KP1;
     double v = 0.0;
-    int32_t node = -1;
-    if (cc < ncb) {
-      node = c2g[(c0 + cc) * nloc + l];
-      v = minv[node] == 0.0 ? 0.0 : x[node];
-      if (minv[node] == 0.0) node = -1;
+    if (cc < ncb && l < nloc) {
+      const int32_t node = c2g[(c0 + cc) * nloc + l];
+      if (minv[node] != 0.0) v = x[node];
     }
-    xs[cc][l] = v;
-    gs[cc][l] = node;
+    xs[i] = v;
   }
   __syncthreads();
-  const int t = threadIdx.x;
-  const int l0 = t, l1 = t + 256;
-  double a0[STIFF_CPB], a1[STIFF_CPB];
-#pragma unroll
-  for (int cc = 0; cc < STIFF_CPB; ++cc) a0[cc] = a1[cc] = 0.0;
-  for (int m = 0; m < nloc; ++m) {
-    const double k0 = l0 < nloc ? K[(int64_t)m * nloc + l0] : 0.0;
-    const double k1 = l1 < nloc ? K[(int64_t)m * nloc + l1] : 0.0;
-#pragma unroll
-    for (int cc = 0; cc < STIFF_CPB; ++cc) {
-      const double xv = xs[cc][m];
-      a0[cc] += k0 * xv;
-      a1[cc] += k1 * xv;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, li = lane % 16, lk = lane / 16;
+  // one row block per wave; the work-groups of blockIdx.y share the gather
+  const int rb = 4 * blockIdx.y + wave;
+  if (rb < RB) {
+    // two accumulators (even and odd k steps) halve the dependent MFMA chain
+    v4d_s acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+    const double *kt = Kt + (int64_t)rb * KS * 64 + lane;
+    const double *xb = xs + li * KP1 + lk;
+    int ks = 0;
+#pragma unroll 4
+    for (; ks + 1 < KS; ks += 2) {
+      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(kt[(int64_t)ks * 64], xb[4 * ks], acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(kt[(int64_t)(ks + 1) * 64], xb[4 * ks + 4], acc1,
+                                                  0, 0, 0);
     }
-  }
+    if (ks < KS)
+      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(kt[(int64_t)ks * 64], xb[4 * ks], acc0, 0, 0, 0);
+    const v4d_s acc = acc0 + acc1;
+    // accumulator v of lane l: local row 16 rb + 4 v + l/16 of cell l%16
 #pragma unroll
-  for (int cc = 0; cc < STIFF_CPB; ++cc) {
-    if (cc >= ncb) break;
-    if (l0 < nloc && gs[cc][l0] >= 0) atomicAdd(&y[gs[cc][l0]], a0[cc]);
-    if (l1 < nloc && gs[cc][l1] >= 0) atomicAdd(&y[gs[cc][l1]], a1[cc]);
+    for (int v = 0; v < 4; ++v) {
+      const int row = 16 * rb + 4 * v + lk;
+      if (li < ncb && row < nloc) {
+        const int32_t node = c2g[(c0 + li) * nloc + row];
+        if (minv[node] != 0.0) atomicAdd(&y[node], acc[v]);
+      }
+    }
   }
 }
 
@@ -479,9 +500,14 @@ __global__ void k_sub(int64_t n, const double *__restrict__ a, const double *__r
 
 // ---- Poisson CG with its scalars on the device.  sc[0] r.z, sc[1] p.Ap,
 // sc[2] r.r, sc[3] new r.z, sc[4] done flag, sc[5] iterations, sc[6] the
-// squared stopping threshold.  Every kernel of an iteration returns at once
-// when the flag is set, so the host can queue iterations in batches and
-// still stop after the same iteration as a loop that tests r.r each time.
+// squared stopping threshold, sc[7] beta.  Every kernel of an iteration
+// returns at once when the flag is set, so the host can queue iterations in
+// batches and still stop after the same iteration as a loop that tests r.r
+// each time.  The reductions go through CG_NB per-work-group partial sums
+// that are added in a fixed order (no atomics: the result does not depend
+// on timing).
+constexpr int CG_NB = 1024;
+
 __device__ inline double block_sum(double v, double *red) {
   red[threadIdx.x] = v;
   __syncthreads();
@@ -492,15 +518,19 @@ __device__ inline double block_sum(double v, double *red) {
   return red[0];
 }
 
-__global__ void k_cg_zero(int64_t n, double *__restrict__ y, const double *__restrict__ sc) {
-  if (sc[4] != 0.0) return;
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < n) y[i] = 0.0;
+// sum of part[0 .. CG_NB) by one work-group of 256 threads, fixed order
+__device__ inline double sum_parts(const double *__restrict__ part, double *red) {
+  double a = 0.0;
+  for (int i = threadIdx.x; i < CG_NB; i += 256) a += part[i];
+  const double t = block_sum(a, red);
+  __syncthreads();
+  return t;
 }
 
 __global__ __launch_bounds__(256) void k_cg_pap(int64_t n, const double *__restrict__ p,
                                                 const double *__restrict__ Ap,
-                                                double *__restrict__ sc) {
+                                                double *__restrict__ part,
+                                                const double *__restrict__ sc) {
   __shared__ double red[256];
   if (sc[4] != 0.0) return;
   double acc = 0.0;
@@ -508,19 +538,22 @@ __global__ __launch_bounds__(256) void k_cg_pap(int64_t n, const double *__restr
        i += (int64_t)gridDim.x * blockDim.x)
     acc += p[i] * Ap[i];
   const double t = block_sum(acc, red);
-  if (threadIdx.x == 0) atomicAdd(&sc[1], t);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
-// phi += alpha p, r -= alpha Ap, z = r / diag (interior), r.r and r.z
+// alpha = r.z / p.Ap (every work-group adds the p.Ap partials itself, in the
+// same order); phi += alpha p, r -= alpha Ap, z = r / diag (interior);
+// partial sums of r.r and r.z
 __global__ __launch_bounds__(256) void k_cg_update(int64_t n, const double *__restrict__ p,
                                                    const double *__restrict__ Ap,
                                                    const double *__restrict__ d,
                                                    const double *__restrict__ minv,
                                                    double *__restrict__ phi, double *__restrict__ r,
-                                                   double *__restrict__ z, double *__restrict__ sc) {
+                                                   double *__restrict__ z, double *__restrict__ part,
+                                                   const double *__restrict__ sc) {
   __shared__ double red[256];
   if (sc[4] != 0.0) return;
-  const double alpha = sc[0] / sc[1];
+  const double alpha = sc[0] / sum_parts(part, red);
   double rr = 0.0, rz = 0.0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
@@ -536,27 +569,39 @@ __global__ __launch_bounds__(256) void k_cg_update(int64_t n, const double *__re
   __syncthreads();
   const double t2 = block_sum(rz, red);
   if (threadIdx.x == 0) {
-    atomicAdd(&sc[2], t1);
-    atomicAdd(&sc[3], t2);
+    part[CG_NB + blockIdx.x] = t1;
+    part[2 * CG_NB + blockIdx.x] = t2;
   }
 }
 
-__global__ void k_cg_pupdate(int64_t n, const double *__restrict__ z, double *__restrict__ p,
-                             const double *__restrict__ sc) {
+// end of an iteration: r.r and the new r.z from their partials, the
+// iteration count, the stopping test, beta, and r.z for the next iteration
+__global__ __launch_bounds__(256) void k_cg_next(const double *__restrict__ part,
+                                                 double *__restrict__ sc) {
+  __shared__ double red[256];
   if (sc[4] != 0.0) return;
-  const double beta = sc[3] / sc[0];
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < n) p[i] = z[i] + beta * p[i];
+  const double rr = sum_parts(part + CG_NB, red);
+  const double rz = sum_parts(part + 2 * CG_NB, red);
+  if (threadIdx.x == 0) {
+    sc[2] = rr;
+    sc[3] = rz;
+    sc[5] += 1.0;
+    if (rr <= sc[6]) sc[4] = 1.0;
+    sc[7] = rz / sc[0];
+    sc[0] = rz;
+  }
 }
 
-__global__ void k_cg_next(double *__restrict__ sc) {
+// p = z + beta p, and Ap = 0 for the next stiffness apply
+__global__ void k_cg_pupdate(int64_t n, const double *__restrict__ z, double *__restrict__ p,
+                             double *__restrict__ Ap, const double *__restrict__ sc) {
   if (sc[4] != 0.0) return;
-  sc[5] += 1.0;
-  if (sc[2] <= sc[6]) sc[4] = 1.0;
-  sc[0] = sc[3];
-  sc[1] = 0.0;
-  sc[2] = 0.0;
-  sc[3] = 0.0;
+  const double beta = sc[7];
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) {
+    p[i] = z[i] + beta * p[i];
+    Ap[i] = 0.0;
+  }
 }
 
 // slot j <- slot j + 1 for j < m, element by element (each thread reads a
@@ -633,6 +678,10 @@ static efe_status scf_init(efe_ctx *c) {
     if ((st = efe_alloc(c, (void **)pp, nn * 8))) return st;
   if ((st = efe_alloc(c, (void **)&s.cg, 5 * nn * 8))) return st;
   if ((st = efe_alloc(c, (void **)&s.scal, 256 * 8))) return st;
+  if ((st = efe_alloc(c, (void **)&s.part, 3 * CG_NB * 8))) return st;
+  const int64_t kt = (int64_t)c->RB * c->KS * 64;
+  if ((st = efe_alloc(c, (void **)&s.Ktile, kt * 8))) return st;
+  k_tile_K<<<cdiv(kt, 256), 256, 0, c->stream>>>(c->nloc, c->RB, c->KS, c->d_K, s.Ktile);
   HIPCHK(c, hipMemsetAsync(s.phi_rem, 0, nn * 8, c->stream));
   HIPCHK(c, hipMemsetAsync(s.Kdiag, 0, nn * 8, c->stream));
   HIPCHK(c, hipMemsetAsync(s.scal, 0, 256 * 8, c->stream));
@@ -674,15 +723,21 @@ static efe_status scf_init(efe_ctx *c) {
 
 // y = K x on interior nodes; with `done` (device CG flag) every launch
 // returns at once when the flag is set
-static efe_status stiff_apply(efe_ctx *c, const double *x, double *y, const double *sc = nullptr) {
-  if (sc)
-    k_cg_zero<<<cdiv(c->n_nodes, 256), 256, 0, c->stream>>>(c->n_nodes, y, sc);
-  else
-    HIPCHK(c, hipMemsetAsync(y, 0, c->n_nodes * 8, c->stream));
-  k_stiff_apply_all<<<cdiv(c->n_cells, STIFF_CPB), 256, 0, c->stream>>>(
-      c->n_cells, c->nloc, c->d_c2g, c->d_K, x, c->d_minv, y, sc ? sc + 4 : nullptr);
+// y += K x (sc: CG scalars whose done flag turns the launch into a no-op)
+static efe_status stiff_add(efe_ctx *c, const double *x, double *y, const double *sc = nullptr) {
+  const size_t shm = (size_t)STIFF_CELLS * (4 * c->KS + 1) * 8;
+  const dim3 grid((unsigned)cdiv(c->n_cells, STIFF_CELLS), (unsigned)cdiv(c->RB, 4));
+  k_stiff_apply_all<<<grid, 256, shm, c->stream>>>(
+      c->n_cells, c->nloc, c->RB, c->KS, c->d_c2g, S(c).Ktile, x, c->d_minv, y,
+      sc ? sc + 4 : nullptr);
   HIPCHK(c, hipGetLastError());
   return EFE_OK;
+}
+
+// y = K x
+static efe_status stiff_apply(efe_ctx *c, const double *x, double *y) {
+  HIPCHK(c, hipMemsetAsync(y, 0, c->n_nodes * 8, c->stream));
+  return stiff_add(c, x, y);
 }
 
 static efe_status dot_host(efe_ctx *c, int64_t n, const double *a, const double *b, double *res) {
@@ -726,19 +781,20 @@ static efe_status poisson(efe_ctx *c, const double *fq, const double *sub, doubl
   // iterations in batches of 16 with the scalars on the device; the loop
   // stops after the first iteration that meets sqrt(r.r) <= rtol |b|
   double *sc = s.scal + 96;
-  const double init[7] = {rz, 0.0, 0.0, 0.0, sqrt(rr) > rtol * bn ? 0.0 : 1.0, 0.0,
-                          (rtol * bn) * (rtol * bn)};   // read by the copy until the sync below
+  const double init[8] = {rz, 0.0, 0.0, 0.0, sqrt(rr) > rtol * bn ? 0.0 : 1.0, 0.0,
+                          (rtol * bn) * (rtol * bn), 0.0};   // read by the copy until the sync below
   HIPCHK(c, hipMemcpyAsync(sc, init, sizeof(init), hipMemcpyHostToDevice, c->stream));
-  const unsigned nb = (unsigned)std::min<int64_t>(cdiv(nn, T), 1024);
+  HIPCHK(c, hipMemsetAsync(Ap, 0, nn * 8, c->stream));   // the loop adds K p into Ap
   double hs[6] = {0, 0, 0, 0, 0, 0};
   while (it < maxit) {
     const int batch = std::min(16, maxit - it);
     for (int q = 0; q < batch; ++q) {
-      if ((st = stiff_apply(c, p, Ap, sc))) return st;
-      k_cg_pap<<<nb, T, 0, c->stream>>>(nn, p, Ap, sc);
-      k_cg_update<<<nb, T, 0, c->stream>>>(nn, p, Ap, s.Kdiag, c->d_minv, phi, r, z, sc);
-      k_cg_pupdate<<<cdiv(nn, T), T, 0, c->stream>>>(nn, z, p, sc);
-      k_cg_next<<<1, 1, 0, c->stream>>>(sc);
+      if ((st = stiff_add(c, p, Ap, sc))) return st;
+      k_cg_pap<<<CG_NB, T, 0, c->stream>>>(nn, p, Ap, s.part, sc);
+      k_cg_update<<<CG_NB, T, 0, c->stream>>>(nn, p, Ap, s.Kdiag, c->d_minv, phi, r, z, s.part,
+                                              sc);
+      k_cg_next<<<1, T, 0, c->stream>>>(s.part, sc);
+      k_cg_pupdate<<<cdiv(nn, T), T, 0, c->stream>>>(nn, z, p, Ap, sc);
     }
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipMemcpyAsync(hs, sc, 6 * 8, hipMemcpyDeviceToHost, c->stream));

@@ -19,8 +19,24 @@ torch = pytest.importorskip("torch")
 SAMPLE = [0, 97, 159]
 
 
+_CAPTURE = None
+
+
+@pytest.fixture(autouse=True, scope="module")
+def _capture_manager(request):
+    # the oracle runs here take minutes: progress lines go out past pytest's
+    # output capture, so that a quiet but working run is not taken for a hang
+    global _CAPTURE
+    _CAPTURE = request.config.pluginmanager.getplugin("capturemanager")
+    yield
+
+
 def _say(*a):
-    print("[gpu-full]", *a, flush=True)
+    if _CAPTURE is not None:
+        with _CAPTURE.global_and_fixture_disabled():
+            print("[gpu-full]", *a, flush=True)
+    else:
+        print("[gpu-full]", *a, flush=True)
 
 
 @pytest.fixture(scope="module")
@@ -58,9 +74,18 @@ def test_apply_full_block(c64):
 
 def test_filter_full_block(c64):
     """One residual filter pass of degree 40 over the 160-vector block with
-    prescribed Ritz-like values; sampled columns against the oracle."""
+    prescribed Ritz-like values; the column of the highest value against the
+    oracle (one oracle run of 41 applies on the full mesh: minutes of CPU
+    time, with progress lines)."""
     from oracle import eigen
     w, s, V0, mask, b, ctx = c64
+    calls = [0]
+
+    def H(x):
+        calls[0] += 1
+        if calls[0] % 5 == 0:
+            _say("oracle filter: H apply", calls[0])
+        return s.apply_H(x)
     N, m = w["nvec"], w["degree"]
     # the filter acts column by column for any values; these span the bound
     # states of the local pseudopotential (lowest near -140 Ha)
@@ -68,13 +93,15 @@ def test_filter_full_block(c64):
     a, amin = lam[-1], -200.0
     Vd = torch.from_numpy(V0).cuda()
     ctx.cheb_filter(Vd, torch.from_numpy(lam).cuda(), m, a, b, amin)
-    got = Vd.cpu().numpy()[:, SAMPLE]
-    ref = eigen.residual_filter(s.apply_H, s.apply_M, s.apply_Minv_tilde, V0[:, SAMPLE],
-                                lam[SAMPLE], a, b, amin, m)
-    err = np.abs(got - ref).max() / np.abs(ref).max()
+    torch.cuda.synchronize()
+    _say("GPU filter done")
     tol = 1e-11 + 1e-14 * s.tilde_condition()
-    _say("filter sampled columns rel err", err, "tol", tol)
-    assert err < tol
+    for j in (N - 1,):
+        ref = eigen.residual_filter(H, s.apply_M, s.apply_Minv_tilde, V0[:, [j]], lam[[j]], a, b,
+                                    amin, m)
+        err = np.abs(Vd[:, j].cpu().numpy() - ref[:, 0]).max() / np.abs(ref).max()
+        _say("filter column", j, "rel err", err, "tol", tol)
+        assert err < tol
 
 
 def test_rayleigh_ritz_full_block(c64):
