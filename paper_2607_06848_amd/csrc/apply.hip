@@ -385,13 +385,21 @@ __global__ __launch_bounds__(256) void k_kb_project(int ncols, const int32_t *__
   const int lane = threadIdx.x % 64;
   const int c0 = blockIdx.y * 64 * POST_Q;
   double acc[POST_Q] = {0.0, 0.0, 0.0};
-  for (int32_t s = it[1] + wave; s < it[2]; s += 4) {
-    const int64_t node = kbnode[s];
-    const double p = Pc[s];
+  // entries it[1] + wave + 4 i: node numbers and coefficients come in 64 at
+  // a time by vector loads and reach the wave by readlane; clamped columns
+  // keep the row loads unconditional (their sums are not stored)
+  const int32_t s0 = it[1], s1 = it[2];
+  for (int32_t sb = s0 + wave; sb < s1; sb += 256) {
+    const int cnt = min(64, (s1 - sb + 3) / 4);
+    const int32_t sl = min(sb + 4 * lane, s1 - 1);
+    const int32_t nodes = kbnode[sl];
+    const double pv = Pc[sl];
+    for (int i = 0; i < cnt; ++i) {
+      const int64_t node = __builtin_amdgcn_readlane(nodes, i);
+      const double p = lane_bcast(pv, i);
 #pragma unroll
-    for (int q = 0; q < POST_Q; ++q) {
-      const int col = c0 + 64 * q + lane;
-      if (col < ncols) acc[q] += p * Xh[node * ldh + col];
+      for (int q = 0; q < POST_Q; ++q)
+        acc[q] += p * Xh[node * ldh + min(c0 + 64 * q + lane, ncols - 1)];
     }
   }
   if (wave > 0)
@@ -431,35 +439,49 @@ __global__ __launch_bounds__(256) void k_kb_w_pphi(int ncols, int64_t n_enr,
     W[(int64_t)I * ncols + col] = D[I] * (((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane]);
 }
 
-// Y^C[node] += sum_e P^C_e W[atom_e] over the node's projector entries; one
-// wave per node (wave-uniform entry list), three columns per lane.
+// Y^C[node] += sum_e P^C_e W[atom_e] over the node's projector entries.  One
+// wave per 8 consecutive nodes, three columns per lane.  The nodes' entry
+// pointers and (when the group has at most 64 entries, as usual) their
+// entries, contiguous for consecutive nodes, come in by vector loads and
+// reach the wave by readlane.
 __global__ __launch_bounds__(256) void k_kb_expand(int64_t n_nodes, int ncols,
                                                    const int32_t *__restrict__ kbnm_ptr,
                                                    const int32_t *__restrict__ kbnm_atom,
                                                    const double *__restrict__ Pc_nm,
                                                    const double *__restrict__ W,
                                                    double *__restrict__ Y, int64_t ldy) {
-  const int64_t j =
+  const int64_t grp =
       (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
-  if (j >= n_nodes) return;
+  const int64_t n0 = grp * 8;
+  if (n0 >= n_nodes) return;
   const int lane = threadIdx.x % 64;
-  const int32_t e0 = kbnm_ptr[j], e1 = kbnm_ptr[j + 1];
-  if (e0 == e1) return;
+  const int nn = (int)min<int64_t>(8, n_nodes - n0);
+  const int32_t pv = kbnm_ptr[n0 + min(lane, nn)];   // pointers of nodes n0 .. n0 + nn
+  const int32_t eb = __builtin_amdgcn_readlane(pv, 0), ee = __builtin_amdgcn_readlane(pv, nn);
+  if (eb == ee) return;
+  const bool vec = ee - eb <= 64;
+  const int32_t el = min(eb + lane, ee - 1);
+  const int32_t av = kbnm_atom[el];
+  const double cv = Pc_nm[el];
   for (int c0 = 0; c0 < ncols; c0 += 64 * POST_Q) {
-    double acc[POST_Q] = {0.0, 0.0, 0.0};
-    for (int32_t e = e0; e < e1; ++e) {
-      const double p = Pc_nm[e];
-      const double *w = W + (int64_t)kbnm_atom[e] * ncols;
+    for (int j = 0; j < nn; ++j) {
+      const int32_t e0 = __builtin_amdgcn_readlane(pv, j);
+      const int32_t e1 = __builtin_amdgcn_readlane(pv, j + 1);
+      if (e0 == e1) continue;
+      double acc[POST_Q] = {0.0, 0.0, 0.0};
+      for (int32_t e = e0; e < e1; ++e) {
+        const int32_t atom = vec ? __builtin_amdgcn_readlane(av, e - eb) : kbnm_atom[e];
+        const double p = vec ? lane_bcast(cv, e - eb) : Pc_nm[e];
+        const double *w = W + (int64_t)atom * ncols;
+#pragma unroll
+        for (int q = 0; q < POST_Q; ++q) acc[q] += p * w[min(c0 + 64 * q + lane, ncols - 1)];
+      }
+      double *y = Y + (n0 + j) * ldy;
 #pragma unroll
       for (int q = 0; q < POST_Q; ++q) {
         const int col = c0 + 64 * q + lane;
-        if (col < ncols) acc[q] += p * w[col];
+        if (col < ncols) y[col] += acc[q];
       }
-    }
-#pragma unroll
-    for (int q = 0; q < POST_Q; ++q) {
-      const int col = c0 + 64 * q + lane;
-      if (col < ncols) Y[j * ldy + col] += acc[q];
     }
   }
 }
@@ -780,7 +802,7 @@ efe_status efe_apply_H_internal(efe_ctx *c, const double *XC, int64_t ldx, const
                                                                  c->d_kbnm_atom, c->d_Pc_nm, W, Y,
                                                                  ldy);
     else
-      k_kb_expand<<<cdiv(c->n_nodes, 4), 256, 0, c->stream>>>(c->n_nodes, ncols, c->d_kbnm_ptr,
+      k_kb_expand<<<cdiv(c->n_nodes, 32), 256, 0, c->stream>>>(c->n_nodes, ncols, c->d_kbnm_ptr,
                                                               c->d_kbnm_atom, c->d_Pc_nm, W, Y, ldy);
   }
   // enrichment rows
