@@ -30,6 +30,7 @@ sys.path.insert(0, ROOT)
 
 PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15, "hbm": 8.0e12}
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
+COL_CHUNK = 160   # column chunk of the filter and of one cell GEMM launch
 CELL_KERNEL = {"fp64": "k_cell2<double, 1, 10>", "fp32": "k_cell2<float, 1, 10>",
                "bf16": "k_cell_bf16<32>"}
 
@@ -162,6 +163,53 @@ def precision_error(w):
           flush=True)
 
 
+def time_to_scf(args, w, new_run, on_pass):
+    """The time-to-SCF runs named by --scf-runs, each from its own fresh
+    context and seeded start block; returns the time_to_scf record."""
+    import torch
+    from paper_2607_06848_amd import efe
+    deg = w["degree"]
+    from paper_2607_06848_amd import learned
+    model = learned.Model.load(args.model) if os.path.exists(args.model) else None
+    runs = []
+    for name in args.scf_runs.split(","):
+        p, g = name.split("_")
+        if g == "learned" and model is None:
+            log(f"no density model at {args.model}: skipping {name}")
+            continue
+        runs.append((name, PREC[p], model if g == "learned" else None))
+    res = {}
+    for name, prec_k, mdl in runs:
+        log(f"time to SCF: {name}")
+        ctx, V, lam, v0 = new_run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fb, fac = mdl.apply(ctx) if mdl is not None else ctx.density_guess(None)
+        hist = efe.scf_run(ctx, V, lam, v0, deg, tol=1e-5, max_iter=args.max_scf_steps,
+                           prec=prec_k,
+                           passes_first=4, passes=1, progress=on_pass,
+                           log=lambda i, r: log(f" {name} step {i}: E {r['E']:.8f} "
+                                                f"dE {r['dE']:.2e} drho {r['drho']:.2e}"))
+        torch.cuda.synchronize()
+        t_scf = time.perf_counter() - t0
+        ctx.close()
+        res[name] = {"seconds": t_scf, "steps": len(hist),
+                     "filter_passes": sum(h["passes"] for h in hist), "E_Ha": hist[-1]["E"],
+                     "converged": len(hist) > 1 and abs(hist[-1]["dE"]) / len(w["xyz"]) < 1e-5
+                     and hist[-1]["drho"] / hist[-1]["n_el"] < 1e-5,
+                     "last_dE_per_atom": abs(hist[-1]["dE"]) / len(w["xyz"]),
+                     "last_drho_per_electron": hist[-1]["drho"] / hist[-1]["n_el"],
+                     "guess": "learned" if mdl is not None and not fb else "superposition",
+                     "filter_precision": "fp64" if prec_k == 0 else "fp32"}
+        log(f"SCF {name}: {len(hist)} steps, {t_scf:.1f} s, E {hist[-1]['E']:.8f}")
+    if "fp32_learned" in res and "fp64_sad" in res:
+        a, b = res["fp64_sad"], res["fp32_learned"]
+        res["speedup"] = a["seconds"] / b["seconds"]
+        res["dE_per_atom"] = abs(a["E_Ha"] - b["E_Ha"]) / len(w["xyz"])
+    res["tol_Ha_per_atom"] = 1e-5
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -182,6 +230,11 @@ def main():
                     help="one SCF step (Rayleigh-Ritz + first-step passes) in FP64 and in FP32 "
                          "from the same start; print the eigenvalue, density and energy "
                          "differences as one JSON line and exit")
+    ap.add_argument("--max-scf-steps", type=int, default=60,
+                    help="step cap of each time-to-SCF run (a capped run reports converged: false)")
+    ap.add_argument("--scf-only", action="store_true",
+                    help="only the time-to-SCF runs: one JSON line with time_to_scf and no "
+                         "timed steps")
     ap.add_argument("--model", default=os.path.join(ROOT, "paper_2607_06848_amd", "weights",
                                                     "density_c64.npz"),
                     help="trained initial-density network for the mixed + learned SCF run")
@@ -223,6 +276,15 @@ def main():
     def on_pass(i, tf, tr):
         log(f"  pass {i}: filter {tf:.0f} ms, Rayleigh-Ritz {tr:.0f} ms")
 
+    if args.scf_only:
+        ctx.close()
+        del V
+        torch.cuda.empty_cache()
+        print(json.dumps({"workload": w["name"], "natoms": len(w["xyz"]), "vectors": N,
+                          "degree": deg, "time_to_scf": time_to_scf(args, w, new_run, on_pass)}),
+              flush=True)
+        return
+
     kw = dict(prec=prec, passes_first=4, passes=1, progress=on_pass)
     for i in range(args.warmup):
         r = ctx.scf_step(V, lam, v0, deg, **kw)
@@ -255,8 +317,10 @@ def main():
                  ("t_poisson_ms", "t_operators_ms", "t_bound_ms", "t_filter_ms", "t_rr_ms",
                   "t_density_ms", "t_energy_ms", "t_other_ms")}
     # roofline of the dominant kernel: one colour pass of the cell GEMM
+    # one launch multiplies one colour's cells into one column chunk of at
+    # most 160 vectors (wider blocks run chunk by chunk)
     cells_per_launch = ctx.n_cells / 8.0
-    flops_per_launch = 2.0 * ctx.nloc ** 2 * N * cells_per_launch
+    flops_per_launch = 2.0 * ctx.nloc ** 2 * min(N, COL_CHUNK) * cells_per_launch
     avg_cell_s = cell_ms * 1e-3 / max(ncell_l, 1)
     achieved = flops_per_launch / avg_cell_s
     peak = PEAK[args.prec]
@@ -288,41 +352,7 @@ def main():
                      "launch_ms": avg_cell_s * 1e3, "flops_per_launch": flops_per_launch},
     }
     if not args.no_scf:
-        from paper_2607_06848_amd import learned
-        model = learned.Model.load(args.model) if os.path.exists(args.model) else None
-        runs = []
-        for name in args.scf_runs.split(","):
-            p, g = name.split("_")
-            if g == "learned" and model is None:
-                log(f"no density model at {args.model}: skipping {name}")
-                continue
-            runs.append((name, PREC[p], model if g == "learned" else None))
-        res = {}
-        for name, prec_k, mdl in runs:
-            log(f"time to SCF: {name}")
-            ctx, V, lam, v0 = new_run()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            fb, fac = mdl.apply(ctx) if mdl is not None else ctx.density_guess(None)
-            hist = efe.scf_run(ctx, V, lam, v0, deg, tol=1e-5, max_iter=60, prec=prec_k,
-                               passes_first=4, passes=1, progress=on_pass,
-                               log=lambda i, r: log(f" {name} step {i}: E {r['E']:.8f} "
-                                                    f"dE {r['dE']:.2e} drho {r['drho']:.2e}"))
-            torch.cuda.synchronize()
-            t_scf = time.perf_counter() - t0
-            ctx.close()
-            res[name] = {"seconds": t_scf, "steps": len(hist),
-                         "filter_passes": sum(h["passes"] for h in hist), "E_Ha": hist[-1]["E"],
-                         "converged": abs(hist[-1]["dE"]) / len(w["xyz"]) < 1e-5,
-                         "guess": "learned" if mdl is not None and not fb else "superposition",
-                         "filter_precision": "fp64" if prec_k == 0 else "fp32"}
-            log(f"SCF {name}: {len(hist)} steps, {t_scf:.1f} s, E {hist[-1]['E']:.8f}")
-        if "fp32_learned" in res and "fp64_sad" in res:
-            a, b = res["fp64_sad"], res["fp32_learned"]
-            res["speedup"] = a["seconds"] / b["seconds"]
-            res["dE_per_atom"] = abs(a["E_Ha"] - b["E_Ha"]) / len(w["xyz"])
-        res["tol_Ha_per_atom"] = 1e-5
-        out["time_to_scf"] = res
+        out["time_to_scf"] = time_to_scf(args, w, new_run, on_pass)
     if not args.no_cpu:
         log("timing the oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(w)

@@ -234,6 +234,62 @@ __global__ __launch_bounds__(256) void k_enr_pair_proj(
   }
 }
 
+// Potential part of the same projections, on FP64 MFMA: for one (atom, cell)
+// pair, out[l][k] += sum_q N[q][l] (w v s_k phi_k)(x_q), a 343 x 9 product
+// over the cell's Gauss points.  The weighted enrichment values sit in LDS as
+// the B operand (16 columns, zero past nf and past nqp); each wave takes row
+// blocks of N^T (A operand, 16 consecutive entries of a row of N per load).
+typedef double v4d_p __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void k_enr_pair_proj_v(
+    MeshGeo g, EnrParam e, const double *__restrict__ xq1, const double *__restrict__ W3,
+    const double *__restrict__ N3, const double *__restrict__ xyz, const double *__restrict__ nu,
+    const int32_t *__restrict__ pair_atom, const int32_t *__restrict__ pair_cell,
+    const int32_t *__restrict__ lmap, const double *__restrict__ vq, int KQ,
+    double *__restrict__ out_b) {
+  extern __shared__ double sphi[];   // [4 KQ][16]
+  const int pr = blockIdx.x;
+  const int I = pair_atom[pr], cell = pair_cell[pr];
+  const int nf = e.nf, nloc = g.nloc, nqp = g.nqp;
+  for (int q = threadIdx.x; q < 4 * KQ; q += blockDim.x) {
+    double row[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) row[k] = 0.0;
+    if (q < nqp) {
+      double x[3], phi[9];
+      quad_point(g, xq1, cell, q, x);
+      enr_eval(e, x[0] - xyz[3 * I], x[1] - xyz[3 * I + 1], x[2] - xyz[3 * I + 2], phi, nullptr);
+      const double w = W3[q] * vq[(int64_t)cell * nqp + q];
+#pragma unroll
+      for (int k = 0; k < 9; ++k)
+        if (k < nf) row[k] = w * nu[I * nf + k] * phi[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) sphi[q * 16 + k] = row[k];
+  }
+  __syncthreads();
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, li = lane % 16, lk = lane / 16;
+  const int RB = (nloc + 15) / 16;
+  for (int rb = wave; rb < RB; rb += 4) {
+    const double *np = N3 + min(16 * rb + li, nloc - 1);
+    v4d_p acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int ks = 0; ks < KQ; ++ks) {
+      const int q = min(4 * ks + lk, nqp - 1);   // past nqp: zero rows of sphi
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(np[(int64_t)q * nloc],
+                                                 sphi[(4 * ks + lk) * 16 + li], acc, 0, 0, 0);
+    }
+    // accumulator v of lane l: local node 16 rb + 4 v + l/16, function l%16
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int l = 16 * rb + 4 * v + lk;
+      if (l < nloc && li < nf) {
+        const int32_t sn = lmap[(int64_t)pr * nloc + l];
+        if (sn >= 0) atomicAdd(&out_b[(int64_t)sn * nf + li], acc[v]);
+      }
+    }
+  }
+}
+
 // C = b / m on support nodes
 __global__ void k_scale_by_minv(int64_t n_snodes, int nf, const int32_t *__restrict__ snode,
                                 const double *__restrict__ minv, const double *__restrict__ b,
@@ -771,9 +827,10 @@ efe_status efe_build_operators(efe_ctx *c, const double *vq, int precisions) {
   if (nf > 0 && c->npairs > 0) {
     const int64_t ns = c->n_snodes * nf;
     k_copy<<<cdiv(ns, 256), 256, 0, c->stream>>>(ns, c->d_Bkin_am, c->d_B_am);
-    k_enr_pair_proj<false><<<c->npairs, 256, 0, c->stream>>>(
-        g, e, c->d_xq1, c->d_W3, c->d_N3, c->d_G3, c->d_xyz, c->d_nu, c->d_pair_atom,
-        c->d_pair_cell, c->d_pair_lmap, c->d_vq, c->d_B_am, nullptr);
+    const int KQ = (int)cdiv(c->nqp, 4);
+    k_enr_pair_proj_v<<<c->npairs, 256, (size_t)KQ * 64 * 8, c->stream>>>(
+        g, e, c->d_xq1, c->d_W3, c->d_N3, c->d_xyz, c->d_nu, c->d_pair_atom, c->d_pair_cell,
+        c->d_pair_lmap, c->d_vq, KQ, c->d_B_am);
     k_to_group_major<<<cdiv(c->n_nodes, 256), 256, 0, c->stream>>>(
         c->n_nodes, nf, c->d_nm_ptr, c->d_nm_src, c->d_nm_gslot, c->d_B_am, c->d_Bg);
     k_copy<<<cdiv(ne * ne, 256), 256, 0, c->stream>>>(ne * ne, c->d_Hpp_kin, c->d_Hpp);
