@@ -189,7 +189,8 @@ def time_to_scf(args, w, new_run, on_pass):
                            prec=prec_k,
                            passes_first=4, passes=1, progress=on_pass,
                            log=lambda i, r: log(f" {name} step {i}: E {r['E']:.8f} "
-                                                f"dE {r['dE']:.2e} drho {r['drho']:.2e}"))
+                                                f"dE {r['dE']:.2e} drho {r['drho']:.2e} "
+                                                f"at {time.perf_counter() - t0:.1f} s"))
         torch.cuda.synchronize()
         t_scf = time.perf_counter() - t0
         ctx.close()

@@ -27,6 +27,7 @@ struct ScfState {
   double *cg = nullptr;                                               // r, z, p, Ap, b
   double *Ktile = nullptr;   // cell stiffness in the 16x16x4 MFMA operand layout
   double *part = nullptr;    // per-work-group partial sums of the CG reductions
+  double *ycell = nullptr;   // K x cell by cell, before the gather to nodes
   double *hist = nullptr;                                             // Anderson X, F ring
   double *scal = nullptr;                                             // device scalars
   double *f = nullptr;                                                // occupations [N]
@@ -48,7 +49,7 @@ void efe_scf_free(efe_ctx *c) {
   ScfState &s = *(ScfState *)c->scf;
   void *ptrs[] = {s.rho_at, s.phi_at, s.v_short, s.rho_in, s.rho_out, s.v_in, s.phiq,
                   s.phi_rem, s.phi_out, s.Kdiag, s.cg, s.hist, s.scal, s.f, s.cell_ptr,
-                  s.cell_atom, s.Ktile, s.part};
+                  s.cell_atom, s.Ktile, s.part, s.ycell};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   delete (ScfState *)c->scf;
@@ -161,18 +162,18 @@ __global__ void k_tile_K(int nloc, int RB, int KS, const double *__restrict__ K,
   Kt[idx] = (row < nloc && col < nloc) ? K[(int64_t)row * nloc + col] : 0.0;
 }
 
-// y += K x over all cells in one launch, on FP64 MFMA: a work-group takes 16
+// K x_c for every cell in one launch, on FP64 MFMA: a work-group takes 16
 // cells, whose gathered x form the 16 columns of the B operand (in LDS,
 // zero on boundary nodes and past nloc), and four row blocks of the shared
-// cell stiffness (A operand, MFMA layout), one per wave; the results go to
-// the interior nodes atomically (a node sits in up to 8 cells).
+// cell stiffness (A operand, MFMA layout), one per wave; the products are
+// written cell by cell and summed into the nodes by k_stiff_gather.
 constexpr int STIFF_CELLS = 16;
 __global__ __launch_bounds__(256) void k_stiff_apply_all(int64_t ncells, int nloc, int RB, int KS,
                                                          const int32_t *__restrict__ c2g,
                                                          const double *__restrict__ Kt,
                                                          const double *__restrict__ x,
                                                          const double *__restrict__ minv,
-                                                         double *__restrict__ y,
+                                                         double *__restrict__ ycell,
                                                          const double *__restrict__ done) {
   extern __shared__ double xs[];   // [STIFF_CELLS][4 KS + 1]
   if (done && *done != 0.0) return;
@@ -211,11 +212,70 @@ __global__ __launch_bounds__(256) void k_stiff_apply_all(int64_t ncells, int nlo
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int row = 16 * rb + 4 * v + lk;
-      if (li < ncb && row < nloc) {
-        const int32_t node = c2g[(c0 + li) * nloc + row];
-        if (minv[node] != 0.0) atomicAdd(&y[node], acc[v]);
-      }
+      if (li < ncb && row < nloc) ycell[(c0 + li) * nloc + row] = acc[v];
     }
+  }
+}
+
+// y[node] = sum of ycell over the (up to 8) cells holding the node, in a
+// fixed order (no atomics); zero on boundary nodes.  Node (i, j, k) lies in
+// cells i/p - 1 and i/p along x when i is a multiple of p (inside the mesh),
+// else in cell i/p only; likewise along y and z.  With part, the work-group
+// also leaves its partial sum of x.y there (the p.Ap of CG).
+struct GridDims {
+  int64_t n1x, n1y, n1z;
+  int ncx, ncy, ncz, p, P, nloc;
+};
+__global__ __launch_bounds__(256) void k_stiff_gather(GridDims d, const double *__restrict__ ycell,
+                                                      const double *__restrict__ minv,
+                                                      const double *__restrict__ x,
+                                                      double *__restrict__ y,
+                                                      double *__restrict__ part,
+                                                      const double *__restrict__ done) {
+  __shared__ double red[256];
+  if (done && *done != 0.0) return;
+  const int64_t n = d.n1x * d.n1y * d.n1z;
+  double acc = 0.0;
+  for (int64_t node = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; node < n;
+       node += (int64_t)gridDim.x * blockDim.x) {
+    double v = 0.0;
+    if (minv[node] != 0.0) {
+      const int64_t gi = node % d.n1x, gj = (node / d.n1x) % d.n1y, gk = node / (d.n1x * d.n1y);
+      int cs[3][2], ls[3][2], nc[3];
+      const int64_t g3[3] = {gi, gj, gk};
+      const int ncl[3] = {d.ncx, d.ncy, d.ncz};
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        const int cc = (int)(g3[t] / d.p), a = (int)(g3[t] % d.p);
+        nc[t] = 0;
+        if (a == 0 && cc > 0) {
+          cs[t][nc[t]] = cc - 1;
+          ls[t][nc[t]++] = d.p;
+        }
+        if (cc < ncl[t]) {
+          cs[t][nc[t]] = cc;
+          ls[t][nc[t]++] = a;
+        }
+      }
+      for (int z = 0; z < nc[2]; ++z)
+        for (int yy = 0; yy < nc[1]; ++yy)
+          for (int xx = 0; xx < nc[0]; ++xx) {
+            const int64_t cell = cs[0][xx] + (int64_t)d.ncx * (cs[1][yy] + (int64_t)d.ncy * cs[2][z]);
+            const int l = ls[0][xx] + d.P * (ls[1][yy] + d.P * ls[2][z]);
+            v += ycell[cell * d.nloc + l];
+          }
+    }
+    y[node] = v;
+    if (part) acc += x[node] * v;
+  }
+  if (part) {
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
   }
 }
 
@@ -527,20 +587,6 @@ __device__ inline double sum_parts(const double *__restrict__ part, double *red)
   return t;
 }
 
-__global__ __launch_bounds__(256) void k_cg_pap(int64_t n, const double *__restrict__ p,
-                                                const double *__restrict__ Ap,
-                                                double *__restrict__ part,
-                                                const double *__restrict__ sc) {
-  __shared__ double red[256];
-  if (sc[4] != 0.0) return;
-  double acc = 0.0;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    acc += p[i] * Ap[i];
-  const double t = block_sum(acc, red);
-  if (threadIdx.x == 0) part[blockIdx.x] = t;
-}
-
 // alpha = r.z / p.Ap (every work-group adds the p.Ap partials itself, in the
 // same order); phi += alpha p, r -= alpha Ap, z = r / diag (interior);
 // partial sums of r.r and r.z
@@ -592,16 +638,13 @@ __global__ __launch_bounds__(256) void k_cg_next(const double *__restrict__ part
   }
 }
 
-// p = z + beta p, and Ap = 0 for the next stiffness apply
+// p = z + beta p
 __global__ void k_cg_pupdate(int64_t n, const double *__restrict__ z, double *__restrict__ p,
-                             double *__restrict__ Ap, const double *__restrict__ sc) {
+                             const double *__restrict__ sc) {
   if (sc[4] != 0.0) return;
   const double beta = sc[7];
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < n) {
-    p[i] = z[i] + beta * p[i];
-    Ap[i] = 0.0;
-  }
+  if (i < n) p[i] = z[i] + beta * p[i];
 }
 
 // slot j <- slot j + 1 for j < m, element by element (each thread reads a
@@ -679,6 +722,7 @@ static efe_status scf_init(efe_ctx *c) {
   if ((st = efe_alloc(c, (void **)&s.cg, 5 * nn * 8))) return st;
   if ((st = efe_alloc(c, (void **)&s.scal, 256 * 8))) return st;
   if ((st = efe_alloc(c, (void **)&s.part, 3 * CG_NB * 8))) return st;
+  if ((st = efe_alloc(c, (void **)&s.ycell, (size_t)c->n_cells * c->nloc * 8))) return st;
   const int64_t kt = (int64_t)c->RB * c->KS * 64;
   if ((st = efe_alloc(c, (void **)&s.Ktile, kt * 8))) return st;
   k_tile_K<<<cdiv(kt, 256), 256, 0, c->stream>>>(c->nloc, c->RB, c->KS, c->d_K, s.Ktile);
@@ -723,21 +767,22 @@ static efe_status scf_init(efe_ctx *c) {
 
 // y = K x on interior nodes; with `done` (device CG flag) every launch
 // returns at once when the flag is set
-// y += K x (sc: CG scalars whose done flag turns the launch into a no-op)
-static efe_status stiff_add(efe_ctx *c, const double *x, double *y, const double *sc = nullptr) {
+// y = K x (sc: CG scalars whose done flag turns the launches into no-ops;
+// part: also the per-work-group partials of x.y)
+static efe_status stiff_apply(efe_ctx *c, const double *x, double *y, const double *sc = nullptr,
+                              double *part = nullptr) {
+  ScfState &s = S(c);
   const size_t shm = (size_t)STIFF_CELLS * (4 * c->KS + 1) * 8;
   const dim3 grid((unsigned)cdiv(c->n_cells, STIFF_CELLS), (unsigned)cdiv(c->RB, 4));
-  k_stiff_apply_all<<<grid, 256, shm, c->stream>>>(
-      c->n_cells, c->nloc, c->RB, c->KS, c->d_c2g, S(c).Ktile, x, c->d_minv, y,
-      sc ? sc + 4 : nullptr);
+  k_stiff_apply_all<<<grid, 256, shm, c->stream>>>(c->n_cells, c->nloc, c->RB, c->KS, c->d_c2g,
+                                                   s.Ktile, x, c->d_minv, s.ycell,
+                                                   sc ? sc + 4 : nullptr);
+  const GridDims d{c->n1[0], c->n1[1], c->n1[2], c->ncell[0], c->ncell[1], c->ncell[2],
+                   c->p,     c->P,     c->nloc};
+  k_stiff_gather<<<CG_NB, 256, 0, c->stream>>>(d, s.ycell, c->d_minv, x, y, part,
+                                               sc ? sc + 4 : nullptr);
   HIPCHK(c, hipGetLastError());
   return EFE_OK;
-}
-
-// y = K x
-static efe_status stiff_apply(efe_ctx *c, const double *x, double *y) {
-  HIPCHK(c, hipMemsetAsync(y, 0, c->n_nodes * 8, c->stream));
-  return stiff_add(c, x, y);
 }
 
 static efe_status dot_host(efe_ctx *c, int64_t n, const double *a, const double *b, double *res) {
@@ -784,17 +829,15 @@ static efe_status poisson(efe_ctx *c, const double *fq, const double *sub, doubl
   const double init[8] = {rz, 0.0, 0.0, 0.0, sqrt(rr) > rtol * bn ? 0.0 : 1.0, 0.0,
                           (rtol * bn) * (rtol * bn), 0.0};   // read by the copy until the sync below
   HIPCHK(c, hipMemcpyAsync(sc, init, sizeof(init), hipMemcpyHostToDevice, c->stream));
-  HIPCHK(c, hipMemsetAsync(Ap, 0, nn * 8, c->stream));   // the loop adds K p into Ap
   double hs[6] = {0, 0, 0, 0, 0, 0};
   while (it < maxit) {
     const int batch = std::min(16, maxit - it);
     for (int q = 0; q < batch; ++q) {
-      if ((st = stiff_add(c, p, Ap, sc))) return st;
-      k_cg_pap<<<CG_NB, T, 0, c->stream>>>(nn, p, Ap, s.part, sc);
+      if ((st = stiff_apply(c, p, Ap, sc, s.part))) return st;   // Ap and the p.Ap partials
       k_cg_update<<<CG_NB, T, 0, c->stream>>>(nn, p, Ap, s.Kdiag, c->d_minv, phi, r, z, s.part,
                                               sc);
       k_cg_next<<<1, T, 0, c->stream>>>(s.part, sc);
-      k_cg_pupdate<<<cdiv(nn, T), T, 0, c->stream>>>(nn, z, p, Ap, sc);
+      k_cg_pupdate<<<cdiv(nn, T), T, 0, c->stream>>>(nn, z, p, sc);
     }
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipMemcpyAsync(hs, sc, 6 * 8, hipMemcpyDeviceToHost, c->stream));
