@@ -39,7 +39,6 @@ __device__ inline int64_t xcd_block(const XcdSplit &x) {
 // group-major coefficients (uniform over the wave, so they come through the
 // scalar cache): Xh = s X^C - C^T X^E and Y^C = B^T X^E.
 constexpr int PRE_Q = 3;
-constexpr int PRE_LDS_SLOTS = 24;   // (group, atom) slots a work-group stages in LDS
 __global__ __launch_bounds__(256) void k_pre(int64_t n_nodes, int ncols, const double *__restrict__ XC,
                                              int64_t ldx, const double *__restrict__ scale,
                                              const double *__restrict__ minv,
@@ -49,26 +48,9 @@ __global__ __launch_bounds__(256) void k_pre(int64_t n_nodes, int ncols, const d
                                              const double *__restrict__ Cg,
                                              const double *__restrict__ Bg, int nf,
                                              double *__restrict__ Xh, int64_t ldh,
-                                             double *Y, int64_t ldy, const RecurIn rec) {
-  // The coefficient blocks of the work-group's four groups are consecutive
-  // slots; when they fit, one coalesced vector copy puts them in LDS and the
-  // waves read them there (as wave-uniform scalar loads they arrived one
-  // cache miss at a time).  Otherwise they are read from memory.
-  __shared__ double cs[PRE_LDS_SLOTS * 9 * 8], bs[PRE_LDS_SLOTS * 9 * 8];
-  const int64_t ngroups = (n_nodes + 7) / 8;
-  const int64_t g0 = (int64_t)blockIdx.x * 4;
-  const int32_t sa = g_ptr[g0], sb = g_ptr[min<int64_t>(g0 + 4, ngroups)];
-  const int n8 = nf * 8;
-  const bool staged = (sb - sa) <= PRE_LDS_SLOTS && nf <= 9;
-  if (staged) {
-    const int cnt = (sb - sa) * n8;
-    for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
-      cs[i] = Cg[(int64_t)sa * n8 + i];
-      bs[i] = Bg[(int64_t)sa * n8 + i];
-    }
-  }
-  __syncthreads();
-  const int64_t grp = g0 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
+                                             double *Y, int64_t ldy) {
+  const int64_t grp =
+      (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
   const int lane = threadIdx.x % 64;
   const int64_t n0 = grp * 8;
   if (n0 >= n_nodes) return;
@@ -90,23 +72,14 @@ __global__ __launch_bounds__(256) void k_pre(int64_t n_nodes, int ncols, const d
       for (int j = 0; j < 8; ++j) {
         // unconditional loads at clamped addresses keep every load of the
         // group in flight at once; the select drops what they brought in
-        const int64_t idx = (n0 + min(j, nn - 1)) * ldx + min(col, ncols - 1);
-        double xv;
-        if (rec.W) {
-          // the block is the next Chebyshev vector, formed here from the
-          // previous apply (rec.W), the last two vectors and G, and stored
-          // over the older one (each element is read before it is written)
-          xv = rec.a * rec.W[idx] + rec.b * rec.Zc[idx] + rec.g * rec.Zp[idx] +
-               rec.a * rec.G[idx] * rec.Cl[min(col, ncols - 1)];
-          if (col < ncols && j < nn) rec.Zp[idx] = xv;
-        } else {
-          xv = XC[idx];
-        }
+        const double xv = XC[(n0 + min(j, nn - 1)) * ldx + min(col, ncols - 1)];
         xh[q][j] = (inner[j] && col < ncols) ? s[j] * xv : 0.0;
         y[q][j] = 0.0;
       }
     }
-    auto atom_terms = [&](const double *cg, const double *bg, const double *xe) {
+    for (int32_t a = a0; a < a1; ++a) {
+      const double *xe = XE + (int64_t)g_atom[a] * nf * lde;
+      const double *cg = Cg + (int64_t)a * nf * 8, *bg = Bg + (int64_t)a * nf * 8;
       for (int k = 0; k < nf; ++k) {
         double v[PRE_Q];
 #pragma unroll
@@ -124,13 +97,6 @@ __global__ __launch_bounds__(256) void k_pre(int64_t n_nodes, int ncols, const d
           }
         }
       }
-    };
-    if (staged) {
-      for (int32_t a = a0; a < a1; ++a)
-        atom_terms(cs + (a - sa) * n8, bs + (a - sa) * n8, XE + (int64_t)g_atom[a] * nf * lde);
-    } else {
-      for (int32_t a = a0; a < a1; ++a)
-        atom_terms(Cg + (int64_t)a * n8, Bg + (int64_t)a * n8, XE + (int64_t)g_atom[a] * nf * lde);
     }
 #pragma unroll
     for (int q = 0; q < PRE_Q; ++q) {
@@ -756,9 +722,7 @@ static void launch_cell2(efe_ctx *c, const T *Ht, const double *Xh, int64_t ldh,
 
 efe_status efe_apply_H_internal(efe_ctx *c, const double *XC, int64_t ldx, const double *scale,
                                 const double *XE, int64_t lde, double *Y, int64_t ldy, int ncols,
-                                int prec, const RecurIn *rec) {
-  if (rec && (ncols == 1 || ldx != ncols))
-    EFE_FAIL(c, EFE_EINVAL, "fused recurrence needs a dense block of more than one column");
+                                int prec) {
   if (!c->have_potential) EFE_FAIL(c, EFE_ESTATE, "no potential set");
   if (ncols <= 0) return EFE_OK;
   if ((prec == EFE_FP32 && !c->have32) || (prec == EFE_BF16 && !c->have16))
@@ -787,7 +751,7 @@ efe_status efe_apply_H_internal(efe_ctx *c, const double *XC, int64_t ldx, const
       k_pre<<<cdiv(c->n_nodes, 32), 256, 0, c->stream>>>(c->n_nodes, ncols, XC, ldx, scale,
                                                          c->d_minv, XE, lde, c->d_g_ptr,
                                                          c->d_g_atom, c->d_Cg, c->d_Bg, nf, Xh, ldh,
-                                                         Y, ldy, rec ? *rec : RecurIn{});
+                                                         Y, ldy);
     efe_timer_end(c, EFE_T_PRE, t);
   }
   // projector coefficients
@@ -876,7 +840,7 @@ efe_status efe_transform_cfe(efe_ctx *c, const double *X, int64_t ldx, double *X
   k_pre<<<cdiv(c->n_nodes, 32), 256, 0, c->stream>>>(c->n_nodes, ncols, X, ldx, nullptr, c->d_minv,
                                                      X + c->n_nodes * ldx, ldx, c->d_g_ptr,
                                                      c->d_g_atom, c->d_Cg, c->d_Bg, c->nf, Xh, ldh,
-                                                     nullptr, 0, RecurIn{});
+                                                     nullptr, 0);
   HIPCHK(c, hipGetLastError());
   return EFE_OK;
 }

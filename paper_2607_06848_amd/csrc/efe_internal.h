@@ -178,21 +178,12 @@ efe_status efe_gram(efe_ctx *ctx, int64_t M, int64_t N, int64_t K, double alpha,
                     const double *A, int64_t lda, const double *B, int64_t ldb,
                     const double *w, double *C, int64_t ldc);
 
-// Chebyshev recurrence folded into the pre pass of an apply: the CFE rows of
-// the applied block are a W + b Zc + g Zp + a G diag(Cl), formed on the fly
-// and stored into Zp (all dense, ld = ncols); W == NULL: a plain apply
-struct RecurIn {
-  const double *W = nullptr, *Zc = nullptr, *G = nullptr, *Cl = nullptr;
-  double *Zp = nullptr;
-  double a = 0.0, b = 0.0, g = 0.0;
-};
-
 // operator applications (apply.hip)
 // Y = H^E X with X given as (XC scaled row-wise by `scale` if non-NULL, XE);
 // prec selects the cell GEMM / projector precision.
 efe_status efe_apply_H_internal(efe_ctx *ctx, const double *XC, int64_t ldx, const double *scale,
                                 const double *XE, int64_t lde, double *Y, int64_t ldy, int ncols,
-                                int prec, const RecurIn *rec = nullptr);
+                                int prec);
 efe_status efe_apply_M_internal(efe_ctx *ctx, const double *X, int64_t ldx, double *Y,
                                 int64_t ldy, int ncols);
 efe_status efe_apply_Minv_internal(efe_ctx *ctx, const double *X, int64_t ldx, double *Y,

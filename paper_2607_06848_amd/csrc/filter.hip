@@ -111,8 +111,6 @@ static efe_status filter_chunk(efe_ctx *c, double *V, const double *lambda, int3
   if ((s = efe_ws(c, 3, blk * 8, (void **)&Za))) return s;
   if ((s = efe_ws(c, 4, blk * 8, (void **)&Zb))) return s;
   if ((s = efe_ws(c, 5, blk * 8, (void **)&W))) return s;
-  double *W2;
-  if ((s = efe_ws(c, 9, blk * 8, (void **)&W2))) return s;
   if ((s = efe_ws(c, 6, (size_t)std::max<int64_t>(c->n_enr, 1) * ncols * 8, (void **)&XE))) return s;
   if ((s = efe_ws(c, 7, (size_t)(m + 1) * ncols * 8, (void **)&Cl))) return s;
   if ((s = efe_ws(c, 8, (size_t)(m + 1) * 8, (void **)&dsig))) return s;
@@ -150,65 +148,15 @@ static efe_status filter_chunk(efe_ctx *c, double *V, const double *lambda, int3
   if ((s = efe_apply_M_internal(c, V, ld, Zb, ncols, ncols))) return s;
   double *Zc = Za, *Zp = Zb;
   k_residual_init<<<nb, T, 0, c->stream>>>(rows, ncols, W, Zb, lambda, sig[1] / e, G, Zc, Zp);
-  // Degree step k applies H to Z_{k-1}.  From k = 3 on, Z_{k-1} itself (the
-  // recurrence on W = H Z_{k-2}, Z_{k-2}, Z_{k-3} and G) is formed inside
-  // that apply's pre pass and stored over Z_{k-3}; only its few enrichment
-  // rows are formed first, by a small launch, for the block inverse.  The
-  // applies alternate between two output blocks, so that the pass reading
-  // one W writes the other.  The recurrence's H applies run in the
-  // requested precision; G stays FP64.
-  double *Wc = W, *Wn = W2;
-  const int64_t enr_off = nn * ncols, enr_n = rows - nn;
   for (int k = 2; k <= m; ++k) {
-    if (k == 2) {
-      if ((s = efe_enr_block_inv(c, Zc + enr_off, ncols, XE, ncols, ncols))) return s;
-      if ((s = efe_apply_H_internal(c, Zc, ncols, c->d_minv, XE, ncols, Wn, ncols, ncols,
-                                    prm->prec)))
-        return s;
-    } else if (ncols == 1) {   // single column: the recurrence as its own launch
-      const double a = 2.0 * sig[k - 1] / e;
-      const int t = efe_timer_begin(c, EFE_T_RECUR);
-      k_recur<<<nb, T, 0, c->stream>>>(rows, ncols, a, -cc * a, -sig[k - 2] * sig[k - 1], Wc, Zc,
-                                       Zp, G, Cl + (int64_t)(k - 2) * ncols, Zp);
-      efe_timer_end(c, EFE_T_RECUR, t);
-      if ((s = efe_enr_block_inv(c, Zp + enr_off, ncols, XE, ncols, ncols))) return s;
-      if ((s = efe_apply_H_internal(c, Zp, ncols, c->d_minv, XE, ncols, Wn, ncols, ncols,
-                                    prm->prec)))
-        return s;
-      std::swap(Zc, Zp);
-    } else {
-      const double a = 2.0 * sig[k - 1] / e;
-      const double *clk = Cl + (int64_t)(k - 2) * ncols;
-      if (enr_n > 0) {
-        const int t = efe_timer_begin(c, EFE_T_RECUR);
-        k_recur<<<cdiv(enr_n * ncols, T), T, 0, c->stream>>>(
-            enr_n, ncols, a, -cc * a, -sig[k - 2] * sig[k - 1], Wc + enr_off, Zc + enr_off,
-            Zp + enr_off, G + enr_off, clk, Zp + enr_off);
-        efe_timer_end(c, EFE_T_RECUR, t);
-      }
-      if ((s = efe_enr_block_inv(c, Zp + enr_off, ncols, XE, ncols, ncols))) return s;
-      RecurIn rec;
-      rec.W = Wc;
-      rec.Zc = Zc;
-      rec.Zp = Zp;
-      rec.G = G;
-      rec.Cl = clk;
-      rec.a = a;
-      rec.b = -cc * a;
-      rec.g = -sig[k - 2] * sig[k - 1];
-      if ((s = efe_apply_H_internal(c, Zp, ncols, c->d_minv, XE, ncols, Wn, ncols, ncols,
-                                    prm->prec, &rec)))
-        return s;
-      std::swap(Zc, Zp);
-    }
-    std::swap(Wc, Wn);
-  }
-  // Z_m from the last apply (a full launch over all rows)
-  if (m >= 2) {
-    const double a = 2.0 * sig[m] / e;
+    if ((s = efe_enr_block_inv(c, Zc + nn * ncols, ncols, XE, ncols, ncols))) return s;
+    // the recurrence's H applies run in the requested precision; G stays FP64
+    if ((s = efe_apply_H_internal(c, Zc, ncols, c->d_minv, XE, ncols, W, ncols, ncols, prm->prec)))
+      return s;
+    const double a = 2.0 * sig[k] / e;
     const int t = efe_timer_begin(c, EFE_T_RECUR);
-    k_recur<<<nb, T, 0, c->stream>>>(rows, ncols, a, -cc * a, -sig[m - 1] * sig[m], Wc, Zc, Zp, G,
-                                     Cl + (int64_t)(m - 1) * ncols, Zp);
+    k_recur<<<nb, T, 0, c->stream>>>(rows, ncols, a, -cc * a, -sig[k - 1] * sig[k], W, Zc, Zp, G,
+                                     Cl + (int64_t)(k - 1) * ncols, Zp);
     efe_timer_end(c, EFE_T_RECUR, t);
     std::swap(Zc, Zp);
   }
