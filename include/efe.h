@@ -118,7 +118,10 @@ efe_status efe_local_potential(efe_ctx *ctx, double *vq);
  * (1 << EFE_BF16) for the reduced-precision cell matrices to keep as well. */
 efe_status efe_set_potential(efe_ctx *ctx, const double *vq, int32_t precisions);
 
-/* Y = H^E X for ncols vectors (device blocks, rows x ld). */
+/* Y = H^E X for ncols vectors (device blocks, rows x ld).  Blocks wider than
+ * 160 vectors are applied 160 columns at a time.  EFE_EINVAL if n_nodes x 160
+ * reaches 2^31 (32-bit offsets of the cell GEMM's gathers) or an atom has
+ * more than 16 enrichment functions. */
 efe_status efe_apply_H(efe_ctx *ctx, const double *X, double *Y, int32_t ncols, int64_t ld);
 /* Y = H^E X with the cell GEMMs in the given precision (EFE_FP64, or EFE_FP32
  * / EFE_BF16 with FP32 accumulation; the matrices must have been built by

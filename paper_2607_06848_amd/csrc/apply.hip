@@ -10,6 +10,8 @@
 //   expand     Y^C += P^C^T W
 //   enrichment Y^E  = H^phiphi X^E + P^phi^T W + B Xh - C Y^C
 // where s = 1, or 1/m when the caller folds the CFE part of (M~^E)^-1 in.
+#include <algorithm>
+
 #include "efe_device.h"
 
 typedef double v4d __attribute__((ext_vector_type(4)));
@@ -897,11 +899,25 @@ extern "C" efe_status efe_set_potential(efe_ctx *c, const double *vq, int32_t pr
   return efe_build_operators(c, vq, precisions);
 }
 
+// wide blocks go through the apply in column chunks of the cell GEMM's
+// register tile, so its workspaces stay n_nodes x 160
+static efe_status apply_H_chunked(efe_ctx *c, const double *X, double *Y, int32_t ncols,
+                                  int64_t ld, int prec) {
+  efe_status s;
+  for (int32_t j0 = 0; j0 < ncols; j0 += EFE_COL_CHUNK) {
+    const int32_t nc = std::min<int32_t>(EFE_COL_CHUNK, ncols - j0);
+    if ((s = efe_apply_H_internal(c, X + j0, ld, nullptr, X + c->n_nodes * ld + j0, ld, Y + j0, ld,
+                                  nc, prec)))
+      return s;
+  }
+  return EFE_OK;
+}
+
 extern "C" efe_status efe_apply_H(efe_ctx *c, const double *X, double *Y, int32_t ncols,
                                   int64_t ld) {
   efe_status s = check_block(c, X, Y, ncols, ld);
   if (s) return s;
-  return efe_apply_H_internal(c, X, ld, nullptr, X + c->n_nodes * ld, ld, Y, ld, ncols, EFE_FP64);
+  return apply_H_chunked(c, X, Y, ncols, ld, EFE_FP64);
 }
 
 extern "C" efe_status efe_apply_H_prec(efe_ctx *c, const double *X, double *Y, int32_t ncols,
@@ -910,7 +926,7 @@ extern "C" efe_status efe_apply_H_prec(efe_ctx *c, const double *X, double *Y, i
   if (s) return s;
   if (prec != EFE_FP64 && prec != EFE_FP32 && prec != EFE_BF16)
     EFE_FAIL(c, EFE_EINVAL, "bad precision");
-  return efe_apply_H_internal(c, X, ld, nullptr, X + c->n_nodes * ld, ld, Y, ld, ncols, prec);
+  return apply_H_chunked(c, X, Y, ncols, ld, prec);
 }
 
 extern "C" efe_status efe_apply_M(efe_ctx *c, const double *X, double *Y, int32_t ncols,

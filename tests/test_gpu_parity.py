@@ -79,7 +79,8 @@ def test_local_potential(pair):
     assert np.abs(got - vq).max() <= 1e-13 * np.abs(vq).max()
 
 
-@pytest.mark.parametrize("ncols,pad", [(1, 0), (37, 0), (70, 5)])
+# 203 columns: two column chunks of the apply, the second ragged, padded ld
+@pytest.mark.parametrize("ncols,pad", [(1, 0), (37, 0), (70, 5), (203, 3)])
 def test_apply_H(pair, ncols, pad):
     name, w, mesh, s, vq, ctx, vg = pair
     _say("apply_H", name, ncols, pad)
