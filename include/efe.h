@@ -144,7 +144,9 @@ typedef struct {
   int32_t degree;     /* m >= 1 */
   double a, b, a_min; /* unwanted interval (a, b); a_min <= lowest eigenvalue < a */
   int32_t mode;       /* EFE_FILTER_RESIDUAL or EFE_FILTER_STANDARD */
-  int32_t prec;       /* EFE_FP64, EFE_FP32, EFE_BF16 (cell GEMMs, projectors) */
+  int32_t prec;       /* EFE_FP64, EFE_FP32, EFE_BF16: operands of the cell GEMMs of
+                       * the recurrence; projectors, enrichment rows, G and
+                       * V_out stay FP64 */
 } efe_cheb_params;
 
 /* Chebyshev filter of ncols vectors in place (Sec. III.B).  Residual mode
@@ -153,7 +155,9 @@ typedef struct {
  *   Z_k = (2 s_k/e) H M~^-1 Z_{k-1} - (2 c s_k/e) Z_{k-1} - s_{k-1} s_k Z_{k-2}
  *         + (2 s_k/e) G C_{k-1}(Lambda),
  *   V <- M~^-1 Z_m + V C_m(Lambda).
- * Standard mode ignores lambda and applies C_m((M~^E)^-1 H^E) to V. */
+ * Standard mode ignores lambda and applies C_m((M~^E)^-1 H^E) to V.
+ * Blocks wider than 160 vectors are filtered 160 columns at a time (every
+ * column is filtered on its own). */
 efe_status efe_cheb_filter(efe_ctx *ctx, double *V, const double *lambda, int32_t ncols,
                            int64_t ld, const efe_cheb_params *prm);
 
