@@ -194,20 +194,27 @@ __global__ __launch_bounds__(256) void k_stiff_apply_all(int64_t ncells, int nlo
   // one row block per wave; the work-groups of blockIdx.y share the gather
   const int rb = 4 * blockIdx.y + wave;
   if (rb < RB) {
-    // two accumulators (even and odd k steps) halve the dependent MFMA chain
-    v4d_s acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+    // four accumulators (k step mod 4) quarter the dependent MFMA chain; the
+    // A fragments of eight k steps are loaded ahead of their MFMAs
+    v4d_s acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = acc0, acc2 = acc0, acc3 = acc0;
     const double *kt = Kt + (int64_t)rb * KS * 64 + lane;
     const double *xb = xs + li * KP1 + lk;
     int ks = 0;
-#pragma unroll 4
-    for (; ks + 1 < KS; ks += 2) {
-      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(kt[(int64_t)ks * 64], xb[4 * ks], acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(kt[(int64_t)(ks + 1) * 64], xb[4 * ks + 4], acc1,
-                                                  0, 0, 0);
+    for (; ks + 7 < KS; ks += 8) {
+      double a[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a[u] = kt[(int64_t)(ks + u) * 64];
+#pragma unroll
+      for (int u = 0; u < 8; u += 4) {
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], xb[4 * (ks + u)], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u + 1], xb[4 * (ks + u + 1)], acc1, 0, 0, 0);
+        acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u + 2], xb[4 * (ks + u + 2)], acc2, 0, 0, 0);
+        acc3 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u + 3], xb[4 * (ks + u + 3)], acc3, 0, 0, 0);
+      }
     }
-    if (ks < KS)
+    for (; ks < KS; ++ks)
       acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(kt[(int64_t)ks * 64], xb[4 * ks], acc0, 0, 0, 0);
-    const v4d_s acc = acc0 + acc1;
+    const v4d_s acc = (acc0 + acc1) + (acc2 + acc3);
     // accumulator v of lane l: local row 16 rb + 4 v + l/16 of cell l%16
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
