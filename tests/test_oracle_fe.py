@@ -124,3 +124,31 @@ def test_harmonic_oscillator_levels_converge():
         errs.append(np.abs(ev - g["levels"][:4]).max())
     assert errs[1] < errs[0] / 5
     assert errs[1] < 1e-3
+
+
+def test_support_cells_against_sampled_boxes():
+    """Support cells of a sphere, checked cell by cell by the nearest of a
+    dense grid of points in each cell box: a cell whose sampled distance is
+    below r_c - (sampling error) must be listed, one whose sampled distance
+    exceeds r_c + (sampling error) must not."""
+    from oracle import enrich
+    m = fe.Mesh([0.0, 0.0, 0.0], [10.0, 8.0, 9.0], [5, 4, 6], 2, 3)
+    rng = np.random.default_rng(7)
+    for _ in range(3):
+        center = rng.uniform([1.0, 1.0, 1.0], [9.0, 7.0, 8.0])
+        rc = rng.uniform(1.5, 4.0)
+        got = set(enrich.support_cells(m, center, rc).tolist())
+        s = np.linspace(0.0, 1.0, 21)
+        P = np.stack(np.meshgrid(s, s, s, indexing="ij"), -1).reshape(-1, 3)
+        err = 0.5 * np.linalg.norm(np.asarray(m.h, float)) / 20.0   # half a sample diagonal
+        for cid in range(m.n_cells):
+            cx = cid % 5
+            cy = (cid // 5) % 4
+            cz = cid // 20
+            lo = np.asarray(m.lo, float) + np.array([cx, cy, cz]) * np.asarray(m.h, float)
+            pts = lo + P * np.asarray(m.h, float)
+            dmin = np.linalg.norm(pts - center, axis=1).min()
+            if dmin < rc - err:
+                assert cid in got, (cid, dmin, rc)
+            if dmin - err > rc:
+                assert cid not in got, (cid, dmin, rc)
