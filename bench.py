@@ -241,8 +241,8 @@ def main():
                     help="trained initial-density network for the mixed + learned SCF run")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path shards by "
-              "vector columns, see DESIGN.md", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the path is measured on "
+              "one GPU; it would shard over GPUs by vector columns", file=sys.stderr)
         sys.exit(2)
 
     import torch
