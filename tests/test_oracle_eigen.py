@@ -280,3 +280,29 @@ def test_five_pass_solve(eig2):
         assert np.all(l1 <= l0 + 1e-12)
     assert np.all(lam >= ev[:w["nvec"]] - 1e-10)
     assert np.abs(lam[:2] - ev[:2]).max() < 1e-3
+
+
+def test_rayleigh_ritz_on_a_pencil_with_known_spectrum():
+    """A pencil built with known eigenvalues d: H = M^(1/2) Q diag(d) Q^T M^(1/2).
+    On a mixed basis of an invariant subspace, Rayleigh-Ritz returns exactly
+    those eigenvalues, an M-orthonormal basis and zero residuals; on a random
+    subspace its Ritz values lie above the eigenvalues of the same index
+    (Courant-Fischer)."""
+    rng = np.random.default_rng(11)
+    n, k = 40, 6
+    B = rng.standard_normal((n, n))
+    M = B @ B.T + n * np.eye(n)
+    w, U = np.linalg.eigh(M)
+    Mh = U @ np.diag(np.sqrt(w)) @ U.T
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    d = np.sort(rng.uniform(-3.0, 5.0, n))
+    H = Mh @ Q @ np.diag(d) @ Q.T @ Mh
+    X = np.linalg.solve(Mh, Q)          # H X = M X diag(d), X^T M X = I
+    V = X[:, :k] @ rng.standard_normal((k, k))
+    Vr, lam, res = eigen.rayleigh_ritz(lambda Y: H @ Y, lambda Y: M @ Y, V)
+    np.testing.assert_allclose(lam, d[:k], rtol=0, atol=1e-10 * np.abs(d).max())
+    np.testing.assert_allclose(Vr.T @ M @ Vr, np.eye(k), atol=1e-10)
+    assert res.max() < 1e-8 * np.linalg.norm(H)
+    _, lam_r, _ = eigen.rayleigh_ritz(lambda Y: H @ Y, lambda Y: M @ Y,
+                                      rng.standard_normal((n, k)))
+    assert np.all(lam_r >= d[:k] - 1e-10)
