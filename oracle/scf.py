@@ -244,7 +244,11 @@ def effective_potential(es, rho_in, phi_rem_nodes):
 
 
 def total_energy(sys, es, lam, f, rho_out, v_in, kT, phi0=None, rtol=1e-12):
-    """Energies at the output density (reading in the module docstring)."""
+    """Energies at the output density (reading in the module docstring).
+    Parity unpinned as a whole: its parts (band sum, PW92 LDA, Gaussian
+    self and pair energies, the Poisson solve) are pinned, and the converged
+    SCF energy is pinned to be independent of the start, but the assembled
+    total of a cluster has no closed form."""
     mesh = sys.mesh
     e_band = 2.0 * float(np.sum(f * lam))
     exc, _ = lda_pw92(rho_out)
