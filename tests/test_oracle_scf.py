@@ -174,3 +174,52 @@ def test_scf_converges_and_is_guess_independent():
     assert len(h1) < 40 and len(h2) < 40
     assert abs(h1[-1]["E"] - h2[-1]["E"]) < 2e-6
     assert abs(h1[-1]["F"] - h1[-1]["E"]) < 1e-3
+
+
+def test_kerker_on_a_dirichlet_mode():
+    """The lowest Dirichlet mode of the box, sin(pi x/L) sin(pi y/L) sin(pi z/L),
+    is an eigenfunction of -Lap with q^2 = 3 pi^2 / L^2: the preconditioner
+    scales it by q^2 / (q^2 + k0^2) (to the discretization error), and leaves
+    a field of much shorter wavelength nearly unchanged."""
+    L = 10.0
+    mesh = fe.Mesh((0,) * 3, (L,) * 3, (4,) * 3, 6, 7)
+    es = scf.Electrostatics(mesh, np.zeros((0, 3)), np.zeros(0),
+                            dict(rho_alpha=1.0, loc_rc=0.8, loc_amp=0.0, loc_rg=1.0))
+    X = mesh.quad_coords()
+    F = np.prod(np.sin(np.pi * X / L), axis=-1)
+    q2 = 3 * np.pi ** 2 / L ** 2
+    for k0 in (0.5, 1.0, 2.0):
+        PF, it = es.kerker(F, k0)
+        ratio = scf.integrate(mesh, PF * F) / scf.integrate(mesh, F * F)
+        assert ratio == pytest.approx(q2 / (q2 + k0 ** 2), rel=1e-5)
+        assert np.abs(PF - ratio * F).max() < 1e-4
+    Fh = np.prod(np.sin(7 * np.pi * X / L), axis=-1)
+    PF, _ = es.kerker(Fh, 0.5)
+    q2h = 3 * (7 * np.pi) ** 2 / L ** 2
+    ratio = scf.integrate(mesh, PF * Fh) / scf.integrate(mesh, Fh * Fh)
+    assert ratio == pytest.approx(q2h / (q2h + 0.25), abs=2e-3)
+
+
+def test_tau_controlled_passes_reach_the_tolerance():
+    """With tau the first step keeps filtering until every occupied residual
+    is below tau (Sec. III.B); its Ritz values then agree with the dense
+    generalized eigensolve of the same potential."""
+    from oracle import eigen
+    w = wl.make("eig2")
+    mesh = fe.Mesh(w["lo"], w["hi"], w["ncell"], w["p"], w["nq"])
+    s = enrich.EFESystem(mesh, w)
+    es = scf.Electrostatics(mesh, w["xyz"], w["Zs"], w)
+    V0 = wl.random_block(s.rows, w["nvec"], 5)
+    v0 = wl.random_vector(s.rows, 7)
+    kT = 500 * scf.KB_HA_PER_K
+    tau = 1e-9
+    h, _ = scf.scf(s, es, V0, v0, w["nvec"], w["degree"], 8.0, kT, max_iter=1,
+                   passes_first=1, tau=tau, max_passes=40)
+    r = h[0]
+    assert 1 < r["passes"] < 40
+    assert r["max_occ_res"] < tau
+    ev = eigen.dense_ghep(s, 8)
+    assert np.abs(r["lam"][:4] - ev[:4]).max() < 1e-9
+    # without tau the minimum is run
+    h1, _ = scf.scf(s, es, V0, v0, w["nvec"], w["degree"], 8.0, kT, max_iter=1, passes_first=2)
+    assert h1[0]["passes"] == 2 and h1[0]["max_occ_res"] > tau
