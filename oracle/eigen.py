@@ -126,15 +126,23 @@ def rayleigh_ritz(apply_H, apply_M, V, active_mask=None):
 def lanczos_upper_bound(apply_H, apply_Mt, apply_Mt_inv, v0, k=20):
     """Upper bound of the spectrum of M~^-1 H by k Lanczos steps in the M~
     inner product: theta_max(T_k) + |beta_k| (reading of 'a_min <= eps_min',
-    '(a, b)' in Sec. III.B: b must bound the operator being filtered)."""
+    '(a, b)' in Sec. III.B: b must bound the operator being filtered).
+    Each new vector is orthogonalized once more against all earlier ones
+    (classical Gram-Schmidt in the M~ inner product): without it the basis
+    loses orthogonality at a rate set by the conditioning of M~, and two
+    roundings of the same run give different bounds."""
     v = v0 / np.sqrt(v0 @ apply_Mt(v0))
     v_prev = np.zeros_like(v)
     beta_prev = 0.0
     alphas, betas = [], []
+    basis = []
     for j in range(k):
+        basis.append(v)
         w = apply_Mt_inv(apply_H(v))
         alpha = w @ apply_Mt(v)
         w = w - alpha * v - beta_prev * v_prev
+        Q = np.stack(basis, 1)
+        w = w - Q @ (Q.T @ apply_Mt(w))
         beta = np.sqrt(w @ apply_Mt(w))
         alphas.append(alpha)
         betas.append(beta)

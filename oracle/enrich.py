@@ -300,8 +300,8 @@ class EFESystem:
         self.Hpp = self.Hpp_kin + Hv
 
     # ------------------------------------------------------- explicit blocks
-    def _Hcc_full(self, X):
-        Y = self.mesh.cfe_apply(self.vq, X, Hc_all=self._Hc)
+    def _Hcc_full(self, X, cells=None):
+        Y = self.mesh.cfe_apply(self.vq, X, cells=cells, Hc_all=self._Hc)
         if self.nproj:
             Y = Y + self.Pc.T @ (self.D[:, None] * (self.Pc @ X))
         return Y
@@ -324,8 +324,11 @@ class EFESystem:
             Y = Y + self.Pphi.T @ (self.D[:, None] * (self.Pphi @ XE))
         return Y
 
-    def apply_H(self, X):
-        """Y = H^E X with the explicit blocks H^cc_f, H^ec, H^ee."""
+    def apply_H(self, X, cells=None):
+        """Y = H^E X with the explicit blocks H^cc_f, H^ec, H^ee.  With
+        ``cells`` the CFE cell sums run over those cells only, which is exact
+        when X^C and C^T X^E vanish on every node of the other cells (an input
+        supported near a few atoms of a large system)."""
         assert self.vq is not None, "set_potential first"
         X = np.asarray(X, float)
         one = X.ndim == 1
@@ -336,11 +339,11 @@ class EFESystem:
         XE = X[n:]
         Y = np.zeros_like(X)
         if self.nf == 0:
-            Y[:n] = self._Hcc_full(XC)
+            Y[:n] = self._Hcc_full(XC, cells)
             return Y[:, 0] if one else Y
         CtXE = self.C.T @ XE
-        H_XC = self._Hcc_full(XC)
-        H_CtXE = self._Hcc_full(CtXE)
+        H_XC = self._Hcc_full(XC, cells)
+        H_CtXE = self._Hcc_full(CtXE, cells)
         # Y^C = Hcc_f X^C + (H^ec)^T X^E,  (H^ec)^T = B_f^T - Hcc_f C^T
         Y[:n] = H_XC + self._B_full_T(XE) - H_CtXE
         # Y^E = H^ec X^C + H^ee X^E

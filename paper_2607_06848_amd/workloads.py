@@ -74,6 +74,24 @@ def cluster_box(nside, spacing, vacuum):
     return L, vacuum
 
 
+def subcluster(w, center, radius):
+    """The workload w restricted to its atoms within `radius` of `center`
+    (same mesh and parameters; atoms kept in their original order).  Returns
+    (workload, indices of the kept atoms)."""
+    xyz = np.asarray(w["xyz"], float)
+    keep = np.flatnonzero(np.linalg.norm(xyz - np.asarray(center, float), axis=1) < radius)
+    sub = dict(w)
+    sub["xyz"] = xyz[keep]
+    sub["Zs"] = np.asarray(w["Zs"])[keep]
+    return sub, keep
+
+
+def corner_atom(w):
+    """Index of the atom nearest the low corner of the box."""
+    xyz = np.asarray(w["xyz"], float)
+    return int(np.argmin(np.linalg.norm(xyz - np.asarray(w["lo"], float), axis=1)))
+
+
 def make(name, **over):
     """Return a dict with mesh parameters, system parameters and solver
     sizes of a named workload."""
