@@ -149,6 +149,20 @@ typedef struct {
                        * V_out stay FP64 */
 } efe_cheb_params;
 
+/* Round-off amplification of (M~^E)^-1, set when the context is built:
+ * A = max over atoms of ||M^phiphi_II||_F ||(M^ee_II)^-1||_F (an upper bound
+ * of ||M^phiphi_II||_2 / lambda_min(M^ee_II); 1 without enrichment).  M^ee is
+ * the difference of two terms of the size of M^phiphi, so when an enrichment
+ * function lies close to the CFE space the inverse magnifies the rounding of
+ * anything it is applied to by up to A.  Host output. */
+efe_status efe_enrichment_amplification(const efe_ctx *ctx, double *amp);
+
+/* Largest amplification for which the filter accepts EFE_BF16: the BF16 unit
+ * round-off 2^-8 times A must stay below 1, i.e. A <= 256.  Beyond it the
+ * rounding of the cell GEMM operands, magnified by (M~^E)^-1, is as large as
+ * the filtered residual itself and the filter output carries no digits. */
+#define EFE_BF16_MAX_AMPLIFICATION 256.0
+
 /* Chebyshev filter of ncols vectors in place (Sec. III.B).  Residual mode
  * needs the Ritz values `lambda` (device, ncols) paired with V:
  *   G = H V - M V Lambda, Z_1 = (s1/e) G,
@@ -157,7 +171,8 @@ typedef struct {
  *   V <- M~^-1 Z_m + V C_m(Lambda).
  * Standard mode ignores lambda and applies C_m((M~^E)^-1 H^E) to V.
  * Blocks wider than 160 vectors are filtered 160 columns at a time (every
- * column is filtered on its own). */
+ * column is filtered on its own).  EFE_EINVAL for EFE_BF16 when the context's
+ * amplification exceeds EFE_BF16_MAX_AMPLIFICATION (efe_enrichment_amplification). */
 efe_status efe_cheb_filter(efe_ctx *ctx, double *V, const double *lambda, int32_t ncols,
                            int64_t ld, const efe_cheb_params *prm);
 
@@ -178,14 +193,15 @@ efe_status efe_rayleigh_ritz(efe_ctx *ctx, double *V, int32_t ncols, int64_t ld,
  * problem for rho - sum_I rho^(I) (homogeneous Dirichlet, Jacobi CG),
  * Fermi-Dirac occupations, Anderson mixing of rho at the Gauss points. */
 typedef struct {
-  int32_t passes_first;  /* filter + Rayleigh-Ritz passes in the first step */
-  int32_t passes;        /* passes in later steps */
+  int32_t passes_first;  /* filter + Rayleigh-Ritz passes in the first step (minimum) */
+  int32_t passes;        /* passes in later steps (minimum) */
   int32_t degree;        /* Chebyshev degree */
-  int32_t prec;          /* filter precision (EFE_FP64 / EFE_FP32 / EFE_BF16) */
+  int32_t prec;          /* filter precision (EFE_FP64 / EFE_FP32 / EFE_BF16); EFE_BF16 is
+                          * refused as in efe_cheb_filter */
   double kT;             /* smearing temperature in Ha */
   double mix_beta;       /* Anderson damping */
   int32_t mix_history;   /* Anderson history depth, 0..16 */
-  double cg_rtol;        /* Poisson CG relative residual */
+  double cg_rtol;        /* Poisson CG relative residual (also the Kerker solve) */
   int32_t cg_maxit;
   int32_t lanczos_steps; /* spectrum bound per step */
   /* optional: called on the host after every filter + Rayleigh-Ritz pass with
@@ -193,6 +209,17 @@ typedef struct {
    * `progress_user` (progress reports of long steps); NULL: none */
   void (*progress)(int32_t pass, double filter_ms, double rr_ms, void *user);
   void *progress_user;
+  /* Sec. III.B: after the minimum number of passes, further passes run while
+   * the largest residual ||H v_j - lambda_j M v_j||_2 of the occupied states
+   * (f_j > 1e-14 at the current Ritz values) exceeds tau, up to max_passes
+   * passes in the step.  tau <= 0: the minimum only. */
+  double tau;
+  int32_t max_passes;
+  /* Kerker preconditioning of the Anderson update (not in the paper, which
+   * names Anderson mixing only): the mixed residual is multiplied by
+   * q^2 / (q^2 + k0^2), realized on the CFE mesh as F - u with
+   * (K + k0^2 diag(m)) u = k0^2 int F N.  kerker_k0 <= 0: plain Anderson. */
+  double kerker_k0;
 } efe_scf_params;
 
 typedef struct {
@@ -204,7 +231,9 @@ typedef struct {
    * potential; Lanczos bound; Poisson solve and energy sums at rho_out */
   double t_poisson_ms, t_filter_ms, t_rr_ms, t_density_ms, t_other_ms;
   double t_operators_ms, t_bound_ms, t_energy_ms;
-  int32_t iter, passes, cg_iters;
+  /* passes: filter + Rayleigh-Ritz passes run; cg_iters: Poisson CG
+   * iterations (both solves); mix_cg_iters: iterations of the Kerker solve */
+  int32_t iter, passes, cg_iters, mix_cg_iters;
 } efe_scf_report;
 
 /* Input density of the next SCF step (device, n_qpts, Gauss points cell by
@@ -274,7 +303,9 @@ efe_status efe_density_guess(efe_ctx *ctx, const float *params, const float *nor
  * before the first step (it is Rayleigh-Ritz orthonormalized first), the Ritz
  * vectors after each step; lambda (device, N) their values; v0 (device, rows)
  * the Lanczos start vector.  The report (host) carries the energies of the
- * step.  Convergence is decided by the caller (e.g. |dE| / N_atoms < tol). */
+ * step and max_occ_res, the largest occupied-state residual after its last
+ * pass.  Convergence is decided by the caller (e.g. |dE| / N_atoms < tol).
+ * EFE_EINVAL for a bad precision or parameter before any work is done. */
 efe_status efe_scf_step(efe_ctx *ctx, double *V, int32_t ncols, int64_t ld, double *lambda,
                         const double *v0, const efe_scf_params *prm, efe_scf_report *rep);
 

@@ -401,6 +401,12 @@ fail:
   return s;
 }
 
+extern "C" efe_status efe_enrichment_amplification(const efe_ctx *c, double *amp) {
+  if (!c || !amp) return EFE_EINVAL;
+  *amp = c->amplification;
+  return EFE_OK;
+}
+
 extern "C" efe_status efe_get_sizes(const efe_ctx *c, int64_t *s) {
   if (!c || !s) return EFE_EINVAL;
   s[0] = c->rows;

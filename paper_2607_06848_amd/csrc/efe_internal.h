@@ -74,6 +74,7 @@ struct efe_ctx {
   int32_t *d_trip = nullptr;
   double *d_Mpp = nullptr, *d_Mee = nullptr, *d_Hpp_kin = nullptr, *d_Hpp = nullptr;
   double *d_Mee_inv = nullptr;                         // [natoms][nf][nf]
+  double amplification = 1.0;                          // efe_enrichment_amplification
   // (atom, first, end) work items over the support lists, ordered by node region
   int64_t n_enr_items = 0, n_kb_items = 0;
   int64_t enr_items_off[9] = {0}, kb_items_off[9] = {0};   // per-XCD ranges

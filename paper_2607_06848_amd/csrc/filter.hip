@@ -177,6 +177,10 @@ extern "C" efe_status efe_cheb_filter(efe_ctx *c, double *V, const double *lambd
   if (prm->prec != EFE_FP64 && prm->prec != EFE_FP32 && prm->prec != EFE_BF16)
     EFE_FAIL(c, EFE_EINVAL, "bad filter precision");
   if (prm->mode == EFE_FILTER_RESIDUAL && !lambda) EFE_FAIL(c, EFE_EINVAL, "residual mode needs lambda");
+  if (prm->prec == EFE_BF16 && c->amplification > EFE_BF16_MAX_AMPLIFICATION)
+    EFE_FAIL(c, EFE_EINVAL,
+             "BF16 filter refused: enrichment amplification " + std::to_string(c->amplification) +
+                 " exceeds " + std::to_string(EFE_BF16_MAX_AMPLIFICATION));
   if (!c->have_potential) EFE_FAIL(c, EFE_ESTATE, "no potential set");
   efe_status s;
   for (int32_t j0 = 0; j0 < ncols; j0 += EFE_COL_CHUNK) {
@@ -272,6 +276,16 @@ __global__ void k_tridiag_bound(int k, const double *__restrict__ alpha,
   out[0] = hi + fabs(beta[k - 1]);
 }
 
+// w -= sum_{i <= j} c_i V_i (classical Gram-Schmidt against the Lanczos basis)
+__global__ void k_reorth(int64_t n, int j, const double *__restrict__ V, int64_t ldv,
+                         const double *__restrict__ c, double *__restrict__ w) {
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  double acc = 0.0;
+  for (int i = 0; i <= j; ++i) acc += c[i] * V[(int64_t)i * ldv + r];
+  w[r] -= acc;
+}
+
 extern "C" efe_status efe_spectrum_upper_bound(efe_ctx *c, const double *v0, int32_t steps,
                                                double *b_out) {
   if (!c) return EFE_EINVAL;
@@ -280,19 +294,19 @@ extern "C" efe_status efe_spectrum_upper_bound(efe_ctx *c, const double *v0, int
   efe_status s;
   const int64_t rows = c->rows, nn = c->n_nodes, ne = c->n_enr;
   double *buf, *sc;
-  // v, vp, u(=H v), w, x(=M~^-1 u) : 5 vectors
-  if ((s = efe_ws(c, 20, (size_t)rows * 5 * 8, (void **)&buf))) return s;
-  if ((s = efe_ws(c, 21, (size_t)(4 * steps + 8) * 8, (void **)&sc))) return s;
-  double *v = buf, *vp = buf + rows, *u = buf + 2 * rows, *w = buf + 3 * rows, *x = buf + 4 * rows;
-  double *alpha = sc, *beta = sc + steps, *tmp = sc + 2 * steps;   // tmp: 2 per step
-  HIPCHK(c, hipMemsetAsync(sc, 0, (size_t)(4 * steps + 8) * 8, c->stream));
-  HIPCHK(c, hipMemsetAsync(vp, 0, rows * 8, c->stream));
+  // the Lanczos basis V_0 .. V_{steps-1}, then u (= H v), w, x (= M~^-1 u)
+  if ((s = efe_ws(c, 20, (size_t)rows * (steps + 3) * 8, (void **)&buf))) return s;
+  const size_t nsc = (size_t)steps * steps + 4 * (size_t)steps + 8;
+  if ((s = efe_ws(c, 21, nsc * 8, (void **)&sc))) return s;
+  double *Vb = buf, *u = buf + (int64_t)steps * rows, *w = u + rows, *x = w + rows;
+  double *alpha = sc, *beta = sc + steps, *nrm = sc + 2 * steps;   // nrm: steps + 1 slots
+  double *coef = sc + 4 * steps + 8;                               // steps x steps
+  HIPCHK(c, hipMemsetAsync(sc, 0, nsc * 8, c->stream));
   const int T = 256;
   const int nbk = (int)std::min<int64_t>(cdiv(rows, T), 1024);
   // copy of v0 without its boundary rows
   k_mask_copy<<<cdiv(rows, T), T, 0, c->stream>>>(nn, rows, c->d_minv, v0, u);
-  // norm in the M~ inner product: m x^2 on CFE rows + atom blocks
-  double *nrm = tmp + 2 * steps;   // scratch scalar slots
+  // inner product of the M~ norm: m x y on CFE rows + atom blocks
   auto mdot = [&](const double *a, const double *b, double *out) -> efe_status {
     k_dot<<<nbk, T, 0, c->stream>>>(nn, a, b, c->d_m_int, out);
     if (ne) k_enr_block_dot<<<cdiv(c->natoms, 64), 64, 0, c->stream>>>(c->natoms, c->nf, ne, c->d_Mee,
@@ -300,23 +314,30 @@ extern "C" efe_status efe_spectrum_upper_bound(efe_ctx *c, const double *v0, int
     HIPCHK(c, hipGetLastError());
     return EFE_OK;
   };
-  if ((s = mdot(u, u, nrm))) return s;
-  k_scale_by_inv_sqrt<<<cdiv(rows, T), T, 0, c->stream>>>(rows, nrm, u, v, nullptr);
+  if ((s = mdot(u, u, &nrm[steps]))) return s;
+  k_scale_by_inv_sqrt<<<cdiv(rows, T), T, 0, c->stream>>>(rows, &nrm[steps], u, Vb, nullptr);
   for (int j = 0; j < steps; ++j) {
+    double *v = Vb + (int64_t)j * rows;
     if ((s = efe_apply_H_internal(c, v, 1, nullptr, v + nn, 1, u, 1, 1, EFE_FP64))) return s;
     // alpha_j = v^T H v
     k_dot<<<nbk, T, 0, c->stream>>>(rows, v, u, nullptr, &alpha[j]);
     if ((s = efe_apply_Minv_internal(c, u, 1, x, 1, 1))) return s;
-    k_lanczos_update<<<cdiv(rows, T), T, 0, c->stream>>>(rows, x, v, vp, &alpha[j],
-                                                         j > 0 ? &beta[j - 1] : nullptr, w);
-    if ((s = mdot(w, w, &tmp[2 * j]))) return s;
-    // vp <- v ; v <- w / beta_j
-    HIPCHK(c, hipMemcpyAsync(vp, v, rows * 8, hipMemcpyDeviceToDevice, c->stream));
-    k_scale_by_inv_sqrt<<<cdiv(rows, T), T, 0, c->stream>>>(rows, &tmp[2 * j], w, v, &beta[j]);
+    k_lanczos_update<<<cdiv(rows, T), T, 0, c->stream>>>(
+        rows, x, v, j > 0 ? v - rows : v, &alpha[j], j > 0 ? &beta[j - 1] : nullptr, w);
+    // once more against the whole basis
+    double *cj = coef + (int64_t)j * steps;
+    for (int i = 0; i <= j; ++i)
+      if ((s = mdot(Vb + (int64_t)i * rows, w, &cj[i]))) return s;
+    k_reorth<<<cdiv(rows, T), T, 0, c->stream>>>(rows, j, Vb, rows, cj, w);
+    if ((s = mdot(w, w, &nrm[j]))) return s;
+    // v_{j+1} = w / beta_j (the last one is not kept)
+    double *vn = j + 1 < steps ? Vb + (int64_t)(j + 1) * rows : x;
+    k_scale_by_inv_sqrt<<<cdiv(rows, T), T, 0, c->stream>>>(rows, &nrm[j], w, vn, &beta[j]);
   }
-  k_tridiag_bound<<<1, 1, 0, c->stream>>>(steps, alpha, beta, &tmp[2 * steps + 1]);
+  double *res = sc + 4 * steps + 4;
+  k_tridiag_bound<<<1, 1, 0, c->stream>>>(steps, alpha, beta, res);
   HIPCHK(c, hipGetLastError());
-  HIPCHK(c, hipMemcpyAsync(b_out, &tmp[2 * steps + 1], 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(b_out, res, 8, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return EFE_OK;
 }

@@ -31,6 +31,8 @@ struct ScfState {
   double *hist = nullptr;                                             // Anderson X, F ring
   double *scal = nullptr;                                             // device scalars
   double *f = nullptr;                                                // occupations [N]
+  double *kdiag_k = nullptr, *u_k = nullptr, *uq_k = nullptr;         // Kerker solve
+  double kerker_k0 = -1.0;
   int32_t *cell_ptr = nullptr, *cell_atom = nullptr;                  // cell -> atoms
   double e_const = 0.0;
   int iter = 0, nhist = 0, hist_m = 0;
@@ -49,7 +51,7 @@ void efe_scf_free(efe_ctx *c) {
   ScfState &s = *(ScfState *)c->scf;
   void *ptrs[] = {s.rho_at, s.phi_at, s.v_short, s.rho_in, s.rho_out, s.v_in, s.phiq,
                   s.phi_rem, s.phi_out, s.Kdiag, s.cg, s.hist, s.scal, s.f, s.cell_ptr,
-                  s.cell_atom, s.Ktile, s.part, s.ycell};
+                  s.cell_atom, s.Ktile, s.part, s.ycell, s.kdiag_k, s.u_k, s.uq_k};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   delete (ScfState *)c->scf;
@@ -238,7 +240,9 @@ __global__ __launch_bounds__(256) void k_stiff_gather(GridDims d, const double *
                                                       const double *__restrict__ x,
                                                       double *__restrict__ y,
                                                       double *__restrict__ part,
-                                                      const double *__restrict__ done) {
+                                                      const double *__restrict__ done,
+                                                      double shift,
+                                                      const double *__restrict__ m) {
   __shared__ double red[256];
   if (done && *done != 0.0) return;
   const int64_t n = d.n1x * d.n1y * d.n1z;
@@ -271,6 +275,7 @@ __global__ __launch_bounds__(256) void k_stiff_gather(GridDims d, const double *
             const int l = ls[0][xx] + d.P * (ls[1][yy] + d.P * ls[2][z]);
             v += ycell[cell * d.nloc + l];
           }
+      if (shift != 0.0) v += shift * m[node] * x[node];
     }
     y[node] = v;
     if (part) acc += x[node] * v;
@@ -697,11 +702,13 @@ __global__ void k_small_solve(int k, double *__restrict__ A, double *__restrict_
   }
 }
 
-// Anderson update: x = X_k - sum g_i (X_{i+1} - X_i) + beta (F_k - sum g_i (F_{i+1} - F_i))
+// Anderson update: x_bar = X_k - sum g_i (X_{i+1} - X_i),
+// F_bar = F_k - sum g_i (F_{i+1} - F_i); out = x_bar + beta F_bar, or, with
+// Fb, out = x_bar and Fb = F_bar (to be preconditioned first)
 __global__ void k_anderson_update(int64_t n, int k, const double *__restrict__ X,
                                   const double *__restrict__ F, int64_t stride,
                                   const double *__restrict__ g, double beta,
-                                  double *__restrict__ out) {
+                                  double *__restrict__ out, double *__restrict__ Fb) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
   double x = X[(int64_t)k * stride + i], fk = F[(int64_t)k * stride + i];
@@ -711,7 +718,18 @@ __global__ void k_anderson_update(int64_t n, int k, const double *__restrict__ X
     x -= g[j] * dx;
     fk -= g[j] * df;
   }
-  out[i] = x + beta * fk;
+  if (Fb) {
+    out[i] = x;
+    Fb[i] = fk;
+  } else {
+    out[i] = x + beta * fk;
+  }
+}
+
+// y += a x
+__global__ void k_axpy(int64_t n, double a, const double *__restrict__ x, double *__restrict__ y) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) y[i] += a * x[i];
 }
 
 // ------------------------------------------------------------------ host
@@ -720,10 +738,11 @@ static efe_status scf_init(efe_ctx *c) {
   if (s.init) return EFE_OK;
   efe_status st;
   const int64_t nq = c->n_qpts, nn = c->n_nodes;
-  double **qs[] = {&s.rho_at, &s.phi_at, &s.v_short, &s.rho_in, &s.rho_out, &s.v_in, &s.phiq};
+  double **qs[] = {&s.rho_at, &s.phi_at, &s.v_short, &s.rho_in, &s.rho_out, &s.v_in, &s.phiq,
+                   &s.uq_k};
   for (auto pp : qs)
     if ((st = efe_alloc(c, (void **)pp, nq * 8))) return st;
-  double **ns[] = {&s.phi_rem, &s.phi_out, &s.Kdiag};
+  double **ns[] = {&s.phi_rem, &s.phi_out, &s.Kdiag, &s.kdiag_k, &s.u_k};
   for (auto pp : ns)
     if ((st = efe_alloc(c, (void **)pp, nn * 8))) return st;
   if ((st = efe_alloc(c, (void **)&s.cg, 5 * nn * 8))) return st;
@@ -772,12 +791,11 @@ static efe_status scf_init(efe_ctx *c) {
   return EFE_OK;
 }
 
-// y = K x on interior nodes; with `done` (device CG flag) every launch
-// returns at once when the flag is set
-// y = K x (sc: CG scalars whose done flag turns the launches into no-ops;
-// part: also the per-work-group partials of x.y)
+// y = (K + shift diag(m)) x on interior nodes (sc: CG scalars whose done
+// flag turns the launches into no-ops; part: also the per-work-group
+// partials of x.y)
 static efe_status stiff_apply(efe_ctx *c, const double *x, double *y, const double *sc = nullptr,
-                              double *part = nullptr) {
+                              double *part = nullptr, double shift = 0.0) {
   ScfState &s = S(c);
   const size_t shm = (size_t)STIFF_CELLS * (4 * c->KS + 1) * 8;
   const dim3 grid((unsigned)cdiv(c->n_cells, STIFF_CELLS), (unsigned)cdiv(c->RB, 4));
@@ -787,7 +805,7 @@ static efe_status stiff_apply(efe_ctx *c, const double *x, double *y, const doub
   const GridDims d{c->n1[0], c->n1[1], c->n1[2], c->ncell[0], c->ncell[1], c->ncell[2],
                    c->p,     c->P,     c->nloc};
   k_stiff_gather<<<CG_NB, 256, 0, c->stream>>>(d, s.ycell, c->d_minv, x, y, part,
-                                               sc ? sc + 4 : nullptr);
+                                               sc ? sc + 4 : nullptr, shift, c->d_m_int);
   HIPCHK(c, hipGetLastError());
   return EFE_OK;
 }
@@ -803,9 +821,12 @@ static efe_status dot_host(efe_ctx *c, int64_t n, const double *a, const double 
   return EFE_OK;
 }
 
-// phi (in/out, nodes): K phi = 4 pi int (fq - sub) N, Jacobi-preconditioned CG
-static efe_status poisson(efe_ctx *c, const double *fq, const double *sub, double *phi, double rtol,
-                          int maxit, int *iters) {
+// x (in/out, nodes): (K + shift diag(m)) x = scale int (fq - sub) N on the
+// interior nodes, CG with the Jacobi preconditioner diag.  shift = 0,
+// scale = 4 pi is the Poisson problem for phi^rem.
+static efe_status cg_solve(efe_ctx *c, const double *fq, const double *sub, double scale,
+                           double shift, const double *diag, double *phi, double rtol, int maxit,
+                           int *iters) {
   ScfState &s = S(c);
   const int64_t nn = c->n_nodes;
   double *r = s.cg, *z = s.cg + nn, *p = s.cg + 2 * nn, *Ap = s.cg + 3 * nn, *b = s.cg + 4 * nn;
@@ -813,23 +834,22 @@ static efe_status poisson(efe_ctx *c, const double *fq, const double *sub, doubl
   const int T = 256;
   HIPCHK(c, hipMemsetAsync(b, 0, nn * 8, c->stream));
   k_load_vector<<<c->n_cells, 256, 0, c->stream>>>(c->nloc, c->nqp, c->d_c2g, c->d_N3, c->d_W3, fq,
-                                                   sub, c->d_minv, 4.0 * M_PI, b);
-  if ((st = stiff_apply(c, phi, Ap))) return st;
+                                                   sub, c->d_minv, scale, b);
+  if ((st = stiff_apply(c, phi, Ap, nullptr, nullptr, shift))) return st;
   k_sub<<<cdiv(nn, T), T, 0, c->stream>>>(nn, b, Ap, r);
-  k_precond<<<cdiv(nn, T), T, 0, c->stream>>>(nn, r, s.Kdiag, c->d_minv, z);
+  k_precond<<<cdiv(nn, T), T, 0, c->stream>>>(nn, r, diag, c->d_minv, z);
   HIPCHK(c, hipMemcpyAsync(p, z, nn * 8, hipMemcpyDeviceToDevice, c->stream));
-  double rz, bb, rr, pAp;
+  double rz, bb, rr;
   if ((st = dot_host(c, nn, r, z, &rz))) return st;
   if ((st = dot_host(c, nn, b, b, &bb))) return st;
   if ((st = dot_host(c, nn, r, r, &rr))) return st;
   const double bn = sqrt(bb);
   int it = 0;
-  if (bn == 0.0) {   // zero source: zero potential
+  if (bn == 0.0) {   // zero source: zero solution
     HIPCHK(c, hipMemsetAsync(phi, 0, nn * 8, c->stream));
     *iters = 0;
     return EFE_OK;
   }
-  (void)pAp;
   // iterations in batches of 16 with the scalars on the device; the loop
   // stops after the first iteration that meets sqrt(r.r) <= rtol |b|
   double *sc = s.scal + 96;
@@ -840,9 +860,8 @@ static efe_status poisson(efe_ctx *c, const double *fq, const double *sub, doubl
   while (it < maxit) {
     const int batch = std::min(16, maxit - it);
     for (int q = 0; q < batch; ++q) {
-      if ((st = stiff_apply(c, p, Ap, sc, s.part))) return st;   // Ap and the p.Ap partials
-      k_cg_update<<<CG_NB, T, 0, c->stream>>>(nn, p, Ap, s.Kdiag, c->d_minv, phi, r, z, s.part,
-                                              sc);
+      if ((st = stiff_apply(c, p, Ap, sc, s.part, shift))) return st;   // Ap and the p.Ap partials
+      k_cg_update<<<CG_NB, T, 0, c->stream>>>(nn, p, Ap, diag, c->d_minv, phi, r, z, s.part, sc);
       k_cg_next<<<1, T, 0, c->stream>>>(s.part, sc);
       k_cg_pupdate<<<cdiv(nn, T), T, 0, c->stream>>>(nn, z, p, sc);
     }
@@ -853,7 +872,47 @@ static efe_status poisson(efe_ctx *c, const double *fq, const double *sub, doubl
     if (hs[4] != 0.0) break;
   }
   *iters = it;
-  if (hs[4] == 0.0) EFE_FAIL(c, EFE_ENOTCONV, "Poisson CG did not converge");
+  if (hs[4] == 0.0) EFE_FAIL(c, EFE_ENOTCONV, "CG did not converge");
+  return EFE_OK;
+}
+
+// phi (in/out, nodes): K phi = 4 pi int (fq - sub) N (Sec. III.C)
+static efe_status poisson(efe_ctx *c, const double *fq, const double *sub, double *phi, double rtol,
+                          int maxit, int *iters) {
+  ScfState &s = S(c);
+  return cg_solve(c, fq, sub, 4.0 * M_PI, 0.0, s.Kdiag, phi, rtol, maxit, iters);
+}
+
+// d = Kdiag + shift m on interior nodes (1 on the boundary)
+__global__ void k_shift_diag(int64_t n, const double *__restrict__ kd, const double *__restrict__ m,
+                             const double *__restrict__ minv, double shift,
+                             double *__restrict__ d) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  d[i] = minv[i] == 0.0 ? 1.0 : kd[i] + shift * m[i];
+}
+
+// Kerker preconditioner of the mixing (a reading beyond the paper, which
+// names Anderson mixing only): F <- F - u at the Gauss points, with u the CFE
+// solution of (K + k0^2 diag(m)) u = k0^2 int F N.  In Fourier terms this
+// multiplies F by q^2 / (q^2 + k0^2): long-wavelength charge sloshing is
+// damped, short-wavelength components pass.
+static efe_status kerker(efe_ctx *c, double k0, double *Fq, double rtol, int maxit, int *iters) {
+  ScfState &s = S(c);
+  efe_status st;
+  const int64_t nn = c->n_nodes, nq = c->n_qpts;
+  const double sh = k0 * k0;
+  if (s.kerker_k0 != k0) {
+    k_shift_diag<<<cdiv(nn, 256), 256, 0, c->stream>>>(nn, s.Kdiag, c->d_m_int, c->d_minv, sh,
+                                                       s.kdiag_k);
+    s.kerker_k0 = k0;
+  }
+  HIPCHK(c, hipMemsetAsync(s.u_k, 0, nn * 8, c->stream));
+  if ((st = cg_solve(c, Fq, nullptr, sh, sh, s.kdiag_k, s.u_k, rtol, maxit, iters))) return st;
+  k_nodes_to_quad<<<c->n_cells, 256, 0, c->stream>>>(c->nloc, c->nqp, c->d_c2g, c->d_N3, s.u_k,
+                                                     c->d_minv, s.uq_k);
+  k_sub<<<cdiv(nq, 256), 256, 0, c->stream>>>(nq, Fq, s.uq_k, Fq);
+  HIPCHK(c, hipGetLastError());
   return EFE_OK;
 }
 
@@ -893,8 +952,15 @@ extern "C" efe_status efe_scf_step(efe_ctx *c, double *V, int32_t N, int64_t ld,
     EFE_FAIL(c, EFE_EINVAL, "bad arguments");
   if (prm->degree < 1 || prm->passes < 1 || prm->passes_first < 1 || !(prm->kT > 0) ||
       prm->mix_history < 0 || prm->mix_history > 16 || !(prm->cg_rtol > 0) || prm->cg_maxit < 1 ||
-      prm->lanczos_steps < 1)
+      prm->lanczos_steps < 1 || !(prm->tau == prm->tau) || !(prm->kerker_k0 == prm->kerker_k0))
     EFE_FAIL(c, EFE_EINVAL, "bad SCF parameters");
+  if (prm->prec != EFE_FP64 && prm->prec != EFE_FP32 && prm->prec != EFE_BF16)
+    EFE_FAIL(c, EFE_EINVAL, "bad filter precision");
+  if (prm->prec == EFE_BF16 && c->amplification > EFE_BF16_MAX_AMPLIFICATION)
+    EFE_FAIL(c, EFE_EINVAL,
+             "BF16 filter refused: enrichment amplification " + std::to_string(c->amplification) +
+                 " exceeds " + std::to_string(EFE_BF16_MAX_AMPLIFICATION));
+  if (N > 4096) EFE_FAIL(c, EFE_EINVAL, "more than 4096 vectors");
   efe_status st;
   if ((st = scf_init(c))) return st;
   ScfState &s = S(c);
@@ -924,12 +990,33 @@ extern "C" efe_status efe_scf_step(efe_ctx *c, double *V, int32_t N, int64_t ld,
   double t_filter = 0.0, t_rr = 0.0;
   double *res;
   if ((st = efe_ws(c, 30, (size_t)N * 8, (void **)&res))) return st;
+  if (!s.f && (st = efe_alloc(c, (void **)&s.f, 4096 * 8))) return st;
+  double ne_d = ne;
+  double *fo = s.scal + 8;   // mu, band, TS
+  std::vector<double> fh(N), fermi(3), resh(N);
+  // occupations at the current Ritz values and the largest residual among
+  // the occupied states (f > 1e-14)
+  auto occupied_residual = [&](double *out) -> efe_status {
+    k_fermi<<<1, 256, 0, c->stream>>>(N, lambda, ne_d, prm->kT, s.f, fo);
+    HIPCHK(c, hipMemcpyAsync(fh.data(), s.f, N * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(fermi.data(), fo, 3 * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(resh.data(), res, N * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double r = 0.0;
+    for (int j = 0; j < N; ++j)
+      if (fh[j] > 1e-14) r = std::max(r, resh[j]);
+    *out = r;
+    return EFE_OK;
+  };
   if (s.iter == 0) {
     if ((st = efe_rayleigh_ritz(c, V, N, ld, lambda, res))) return st;
   }
-  const int npass = s.iter == 0 ? prm->passes_first : prm->passes;
+  const int npass_min = s.iter == 0 ? prm->passes_first : prm->passes;
+  const int npass_max = std::max(npass_min, prm->tau > 0.0 ? prm->max_passes : npass_min);
   std::vector<double> lh(N);
-  for (int pss = 0; pss < npass; ++pss) {
+  int npass = 0;
+  double max_occ_res = 0.0;
+  for (int pss = 0; pss < npass_max; ++pss) {
     HIPCHK(c, hipMemcpyAsync(lh.data(), lambda, N * 8, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     efe_cheb_params cp{prm->degree, lh[N - 1], b, lh[0], EFE_FILTER_RESIDUAL, prm->prec};
@@ -943,26 +1030,16 @@ extern "C" efe_status efe_scf_step(efe_ctx *c, double *V, int32_t N, int64_t ld,
     HIPCHK(c, hipStreamSynchronize(c->stream));
     const double trr = ms_since(ta);
     t_rr += trr;
+    ++npass;
+    if ((st = occupied_residual(&max_occ_res))) return st;
     if (prm->progress) prm->progress(pss, tfl, trr, prm->progress_user);
+    if (npass >= npass_min && !(prm->tau > 0.0 && max_occ_res > prm->tau)) break;
   }
   auto t2 = std::chrono::steady_clock::now();
-  // 3. occupations and output density
-  if (!s.f && (st = efe_alloc(c, (void **)&s.f, 4096 * 8))) return st;
-  if (N > 4096) EFE_FAIL(c, EFE_EINVAL, "more than 4096 vectors");
-  double *fo = s.scal + 8;   // mu, band, TS
-  k_fermi<<<1, 256, 0, c->stream>>>(N, lambda, ne, prm->kT, s.f, fo);
-  std::vector<double> fh(N), fermi(3), resh(N);
-  HIPCHK(c, hipMemcpyAsync(fh.data(), s.f, N * 8, hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(c, hipMemcpyAsync(fermi.data(), fo, 3 * 8, hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(c, hipMemcpyAsync(resh.data(), res, N * 8, hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(c, hipStreamSynchronize(c->stream));
+  // 3. occupations (from the last pass) and output density
   std::vector<int32_t> cols;
-  double max_occ_res = 0.0;
   for (int j = 0; j < N; ++j)
-    if (fh[j] > 1e-14) {
-      cols.push_back(j);
-      max_occ_res = std::max(max_occ_res, resh[j]);
-    }
+    if (fh[j] > 1e-14) cols.push_back(j);
   // output density, column chunk by column chunk (occupied columns only)
   int32_t *dcols;
   double *Xh;
@@ -1085,8 +1162,18 @@ extern "C" efe_status efe_scf_step(efe_ctx *c, double *V, int32_t N, int64_t ld,
     }
     k_small_solve<<<1, 1, 0, c->stream>>>(k, A, rhs, gam);
   }
-  k_anderson_update<<<cdiv(nq, T), T, 0, c->stream>>>(nq, k, HX, HF, nq, gam, prm->mix_beta,
-                                                      s.rho_in);
+  int kerker_it = 0;
+  if (prm->kerker_k0 > 0.0) {
+    // x_bar in rho_in, F_bar in dfi, then rho_in += beta P F_bar
+    k_anderson_update<<<cdiv(nq, T), T, 0, c->stream>>>(nq, k, HX, HF, nq, gam, prm->mix_beta,
+                                                        s.rho_in, dfi);
+    if ((st = kerker(c, prm->kerker_k0, dfi, prm->cg_rtol, prm->cg_maxit, &kerker_it))) return st;
+    k_axpy<<<cdiv(nq, T), T, 0, c->stream>>>(nq, prm->mix_beta, dfi, s.rho_in);
+  } else {
+    k_anderson_update<<<cdiv(nq, T), T, 0, c->stream>>>(nq, k, HX, HF, nq, gam, prm->mix_beta,
+                                                        s.rho_in, nullptr);
+  }
+  rep->mix_cg_iters = kerker_it;
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipStreamSynchronize(c->stream));
   rep->t_other_ms = ms_since(t3);

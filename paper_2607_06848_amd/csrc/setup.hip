@@ -462,6 +462,22 @@ __global__ void k_block_inv(int natoms, int nf, int64_t n_enr, const double *__r
     for (int j = 0; j < nf; ++j) inv[((int64_t)I * nf + i) * nf + j] = a[i][nf + j];
 }
 
+// amp[I] = ||M^phiphi_II||_F ||(M^ee_II)^-1||_F
+__global__ void k_block_amp(int natoms, int nf, int64_t n_enr, const double *__restrict__ Mpp,
+                            const double *__restrict__ inv, double *__restrict__ amp) {
+  const int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= natoms) return;
+  double a = 0.0, b = 0.0;
+  for (int i = 0; i < nf; ++i)
+    for (int j = 0; j < nf; ++j) {
+      const double m = Mpp[(int64_t)(I * nf + i) * n_enr + I * nf + j];
+      const double v = inv[((int64_t)I * nf + i) * nf + j];
+      a += m * m;
+      b += v * v;
+    }
+  amp[I] = sqrt(a) * sqrt(b);
+}
+
 // Projector: P^C[s] += sum_q W beta N_l (one block per (atom, cell) pair)
 __global__ __launch_bounds__(256) void k_kb_pc(MeshGeo g, double w, double rcut,
                                                const double *__restrict__ xq1,
@@ -765,6 +781,17 @@ efe_status efe_build_enrichment(efe_ctx *c) {
     HIPCHK(c, hipStreamSynchronize(c->stream));
     (void)hipFree(dfail);
     if (hfail) EFE_FAIL(c, EFE_ENUMERIC, "singular atom block of M^ee");
+    double *damp;
+    if ((s = efe_alloc(c, (void **)&damp, (size_t)c->natoms * 8))) return s;
+    k_block_amp<<<cdiv(c->natoms, 64), 64, 0, c->stream>>>(c->natoms, nf, ne, c->d_Mpp,
+                                                           c->d_Mee_inv, damp);
+    std::vector<double> amp(c->natoms);
+    HIPCHK(c, hipMemcpyAsync(amp.data(), damp, (size_t)c->natoms * 8, hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    (void)hipFree(damp);
+    c->amplification = 1.0;
+    for (double a : amp) c->amplification = std::max(c->amplification, a);
   }
   // projectors
   const int np = c->nproj;

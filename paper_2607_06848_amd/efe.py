@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(_HERE, "_lib", "libefe.so")
 
 EFE_FP64, EFE_FP32, EFE_BF16 = 0, 1, 2
 EFE_FILTER_RESIDUAL, EFE_FILTER_STANDARD = 0, 1
+BF16_MAX_AMPLIFICATION = 256.0   # EFE_BF16_MAX_AMPLIFICATION
 STATUS = {0: "EFE_OK", -1: "EFE_EINVAL", -2: "EFE_ENOMEM", -3: "EFE_EHIP",
           -4: "EFE_ENOTCONV", -5: "EFE_ENUMERIC", -6: "EFE_ESTATE"}
 
@@ -50,7 +51,8 @@ class ScfParams(ctypes.Structure):
                 ("mix_beta", ctypes.c_double), ("mix_history", ctypes.c_int32),
                 ("cg_rtol", ctypes.c_double), ("cg_maxit", ctypes.c_int32),
                 ("lanczos_steps", ctypes.c_int32), ("progress", ctypes.c_void_p),
-                ("progress_user", ctypes.c_void_p)]
+                ("progress_user", ctypes.c_void_p), ("tau", ctypes.c_double),
+                ("max_passes", ctypes.c_int32), ("kerker_k0", ctypes.c_double)]
 
 
 PROGRESS = ctypes.CFUNCTYPE(None, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
@@ -62,7 +64,8 @@ class ScfReport(ctypes.Structure):
                 ("E", "F", "E_band", "E_xc", "E_el", "mu", "n_el", "drho", "dE", "max_occ_res",
                  "b", "t_poisson_ms", "t_filter_ms", "t_rr_ms", "t_density_ms", "t_other_ms",
                  "t_operators_ms", "t_bound_ms", "t_energy_ms")] + \
-               [("iter", ctypes.c_int32), ("passes", ctypes.c_int32), ("cg_iters", ctypes.c_int32)]
+               [("iter", ctypes.c_int32), ("passes", ctypes.c_int32), ("cg_iters", ctypes.c_int32),
+                ("mix_cg_iters", ctypes.c_int32)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -81,6 +84,7 @@ _SIGS = {
     "efe_setup_mesh": (ctypes.c_int32, [ctypes.POINTER(MeshDesc), ctypes.POINTER(SystemDesc),
                                         ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
     "efe_get_sizes": (ctypes.c_int32, [ctypes.c_void_p, c_int64_p]),
+    "efe_enrichment_amplification": (ctypes.c_int32, [ctypes.c_void_p, c_double_p]),
     "efe_get_tables": (ctypes.c_int32, [ctypes.c_void_p, c_int32_p, c_int32_p, c_int32_p,
                                         c_uint8_p]),
     "efe_get_support": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, c_int64_p, c_int32_p,
@@ -198,6 +202,11 @@ class Context:
         self._check(L.efe_get_sizes(self.h, sz))
         (self.rows, self.n_nodes, self.n_dof, self.n_enr, self.n_cells, self.n_qpts,
          self.natoms, self.nloc) = [int(v) for v in sz]
+
+    def amplification(self):
+        a = ctypes.c_double()
+        self._check(lib().efe_enrichment_amplification(self.h, ctypes.byref(a)))
+        return a.value
 
     # -------------------------------------------------------------- util
     def _check(self, st):
@@ -356,7 +365,8 @@ class Context:
 
     def scf_step(self, V, lam, v0, degree, passes_first=4, passes=1, prec=EFE_FP64,
                  kT=500 * 3.166811563e-6, mix_beta=0.3, mix_history=8, cg_rtol=1e-12,
-                 cg_maxit=5000, lanczos_steps=20, progress=None):
+                 cg_maxit=5000, lanczos_steps=20, progress=None, tau=0.0, max_passes=0,
+                 kerker_k0=0.0):
         """One SCF step; `progress(pass, filter_ms, rr_ms)` (optional) is called
         after every filter + Rayleigh-Ritz pass."""
         n, ld = self._block(V)
@@ -364,7 +374,8 @@ class Context:
         p = ScfParams(int(passes_first), int(passes), int(degree), int(prec), float(kT),
                       float(mix_beta), int(mix_history), float(cg_rtol), int(cg_maxit),
                       int(lanczos_steps),
-                      ctypes.cast(cb, ctypes.c_void_p) if cb is not None else None, None)
+                      ctypes.cast(cb, ctypes.c_void_p) if cb is not None else None, None,
+                      float(tau), int(max_passes), float(kerker_k0))
         rep = ScfReport()
         self._check(lib().efe_scf_step(self.h, _ptr(V), n, ld, _ptr(lam), _ptr(v0),
                                        ctypes.byref(p), ctypes.byref(rep)))

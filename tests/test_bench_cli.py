@@ -23,6 +23,7 @@ def test_more_than_one_gpu_is_refused():
 def test_help_lists_the_options():
     r = _run("--help")
     assert r.returncode == 0
-    for opt in ("--gpus", "--steps", "--warmup", "--prec", "--workload", "--no-cpu", "--no-scf",
-                "--scf-runs", "--scf-only", "--max-scf-steps", "--profile-applies", "--prec-error"):
+    for opt in ("--gpus", "--steps", "--warmup", "--prec", "--workload", "--no-cpu", "--tau",
+                "--max-passes", "--kerker", "--scf-runs", "--scf-only", "--max-scf-steps",
+                "--profile-applies", "--prec-error"):
         assert opt in r.stdout, opt

@@ -221,3 +221,32 @@ def test_fixed_potential_solve_matches_oracle():
     ctx.close()
     assert max(errs) < 1e-8
     assert np.abs(res.cpu().numpy() - res_ref).max() < 1e-7
+
+
+def test_filter_wide_block_chunks():
+    """One residual filter pass over 203 columns (two column chunks of the
+    filter, 160 + 43) against the oracle's pass over the whole block, on the
+    3-atom p = 6 workload with s, p, d enrichment and projectors."""
+    from oracle import eigen
+    w = wl.make("small", nvec=203)
+    mesh, s, vq = oracle_system(w)
+    mask = np.zeros(s.rows)
+    mask[s.active()] = 1.0
+    V0 = wl.random_block(s.rows, 203, 13) * mask[:, None]
+    V, lam, _ = eigen.rayleigh_ritz(s.apply_H, s.apply_M, V0, mask)
+    b, _, _ = eigen.lanczos_upper_bound(s.apply_H, s.apply_Mtilde, s.apply_Minv_tilde,
+                                        wl.random_vector(s.rows, 7) * mask, 20)
+    m = 6
+    ref = eigen.residual_filter(s.apply_H, s.apply_M, s.apply_Minv_tilde, V, lam, lam[-1], b,
+                                lam[0], m)
+    from paper_2607_06848_amd import efe
+    ctx = efe.Context(w)
+    ctx.set_potential(ctx.local_potential())
+    Vd = dev(V)
+    ctx.cheb_filter(Vd, dev(lam), m, lam[-1], b, lam[0])
+    got = Vd.cpu().numpy()
+    ctx.close()
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    tol = 1e-11 + 1e-14 * s.tilde_condition()
+    _say("203-column filter rel err", err, "tol", tol)
+    assert err < tol
