@@ -34,7 +34,7 @@ sys.path.insert(0, ROOT)
 PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15, "hbm": 8.0e12}
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
 COL_CHUNK = 160   # column chunk of the filter and of one cell GEMM launch
-CELL_KERNEL = {"fp64": "k_cell2<double, 1, 10>", "fp32": "k_cell2<float, 1, 10>",
+CELL_KERNEL = {"fp64": "k_cell3<double, 1, 10, true>", "fp32": "k_cell3<float, 1, 10, true>",
                "bf16": "k_cell_bf16<32>"}
 
 
@@ -354,19 +354,26 @@ def filter_bench(args, w):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     timers = {k: ctx.timing_get(k) for k in ("cell", "pre", "post", "recur", "apply")}
+    names = {"cell": "cell GEMM colour pass", "pre": "projector pass + Y^C start values",
+             "post": "enrichment rows", "recur": "recurrence step (fused apply)",
+             "apply": "plain H apply (G)"}
     ctx.timing(False)
     amp = ctx.amplification()
+    ncp, maxe = ctx.coupling()
     ctx.close()
     ms_step = (t1 - t0) * 1e3 / args.steps
     value = ctx.n_dof * n * deg * args.steps / (t1 - t0)
-    kernels = {k: {"launches": c, "ms_avg": ms / max(c, 1), "ms_per_step": ms / args.steps}
+    kernels = {names[k]: {"launches": c, "ms_avg": ms / max(c, 1), "ms_per_step": ms / args.steps}
                for k, (c, ms) in timers.items()}
     log(f"step {ms_step:.1f} ms; " + ", ".join(f"{k} {v['ms_avg']:.3f} ms x {v['launches']}"
                                               for k, v in kernels.items()))
     # roofline of the cell GEMM colour pass: one launch multiplies one
-    # colour's cells (n_cells / 8) into the chunk's columns
+    # colour's cells (n_cells / 8 on average) into the chunk's columns: the
+    # cell Hamiltonians (2 nloc^2 per cell and vector) and the coupling blocks
+    # E_c and E_c^T (4 nf nloc per coupling pair and vector)
     ncell_l, cell_ms = timers["cell"]
-    flops_per_launch = 2.0 * ctx.nloc ** 2 * n * ctx.n_cells / 8.0
+    nf = ctx.n_enr // max(ctx.natoms, 1)
+    flops_per_launch = (2.0 * ctx.nloc ** 2 * ctx.n_cells + 4.0 * nf * ctx.nloc * ncp) * n / 8.0
     avg_cell_s = cell_ms * 1e-3 / max(ncell_l, 1)
     achieved = flops_per_launch / avg_cell_s
     peak = PEAK[args.prec]
@@ -391,6 +398,7 @@ def filter_bench(args, w):
                                f"residual filter pass over a {n}-column chunk",
                    "n_dof": ctx.n_dof, "rows": ctx.rows, "vectors_per_step": n,
                    "filter_precision": args.prec, "enrichment_amplification": amp,
+                   "coupling_pairs": ncp, "max_enrichment_per_cell": maxe,
                    "full_block_pass_s": full_pass_s,
                    "full_block_pass_rule": f"{w['nvec']} / {n} chunk passes back to back",
                    "kernels": kernels},

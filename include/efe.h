@@ -94,6 +94,13 @@ efe_status efe_setup_mesh(const efe_mesh_desc *mesh, const efe_system_desc *sys,
  * n_cells, n_qpts (n_cells * nq^3), natoms, nloc ((p+1)^3).  Host array. */
 efe_status efe_get_sizes(const efe_ctx *ctx, int64_t *sizes);
 
+/* Coupling of the orthogonalized enrichment to the cells (Sec. II.B, N^E =
+ * phi - C N^C): *ncpairs = number of (atom, cell) pairs whose coupling block
+ * E_c = B_c - C_c H_c is non-zero (every cell holding one of the atom's
+ * support nodes), *max_cell = largest number of enrichment functions coupled
+ * to one cell.  Host outputs (either may be NULL). */
+efe_status efe_get_coupling(const efe_ctx *ctx, int64_t *ncpairs, int64_t *max_cell);
+
 /* Integer mesh tables in host memory (any pointer may be NULL):
  * cell_to_global[n_cells*nloc], colour_order[n_cells] (cells sorted by colour
  * (cx&1)+2(cy&1)+4(cz&1), then id), colour_offsets[9], boundary[n_nodes]. */
@@ -119,13 +126,18 @@ efe_status efe_local_potential(efe_ctx *ctx, double *vq);
 efe_status efe_set_potential(efe_ctx *ctx, const double *vq, int32_t precisions);
 
 /* Y = H^E X for ncols vectors (device blocks, rows x ld).  Blocks wider than
- * 160 vectors are applied 160 columns at a time.  EFE_EINVAL if n_nodes x 160
- * reaches 2^31 (32-bit offsets of the cell GEMM's gathers) or an atom has
- * more than 16 enrichment functions. */
+ * 160 vectors are applied 160 columns at a time.  The apply runs the per-cell
+ * form of T^T Hhat T: the cell GEMM takes [H_c | E_c^T] on the cell's nodes
+ * and enrichment rows, E_c on its nodes for the enrichment rows.  EFE_EINVAL
+ * if n_nodes x 160 reaches 2^31 (32-bit offsets of the cell GEMM's gathers);
+ * efe_setup_mesh refuses systems with more than 768 enrichment functions
+ * coupled to one cell. */
 efe_status efe_apply_H(efe_ctx *ctx, const double *X, double *Y, int32_t ncols, int64_t ld);
 /* Y = H^E X with the cell GEMMs in the given precision (EFE_FP64, or EFE_FP32
  * / EFE_BF16 with FP32 accumulation; the matrices must have been built by
- * efe_set_potential).  The rest of the apply stays FP64. */
+ * efe_set_potential).  The coupling blocks E_c are formed in FP64 and rounded
+ * with the cell matrices; projector and enrichment-block products stay FP64.
+ * EFE_BF16 takes plain CFE systems only (EFE_EINVAL with enrichment). */
 efe_status efe_apply_H_prec(efe_ctx *ctx, const double *X, double *Y, int32_t ncols, int64_t ld,
                             int32_t prec);
 /* Y = M^E X (exact overlap: diag(m) on CFE rows, M^ee on enrichment rows). */
@@ -313,8 +325,10 @@ efe_status efe_scf_step(efe_ctx *ctx, double *V, int32_t ncols, int64_t ld, doub
  * events on the context's stream around the tracked launches; 0 stops.
  * efe_timing_get returns, for a kernel class, the number of recorded launches
  * and their summed duration in milliseconds (synchronizes the stream):
- *   0 one colour pass of the cell GEMM   1 pre pass of an H apply
- *   2 enrichment rows of an H apply      3 residual recurrence update
+ *   0 one colour pass of the cell GEMM
+ *   1 projector coefficients and the Y^C start values of an H apply
+ *   2 enrichment rows of an H apply (partial sums and dense blocks)
+ *   3 whole H apply of a recurrence step (the recurrence fused into it)
  *   4 whole H apply                      5 whole Rayleigh-Ritz
  *   6 colour pass, blocks of <= 16 vectors (e.g. the Lanczos vector)
  *   7 whole H apply, blocks of <= 16 vectors

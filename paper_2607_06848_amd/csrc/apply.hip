@@ -2,13 +2,17 @@
 // Discrete_Eig_Gen_H), the exact overlap M^E and its approximate inverse
 // (Eq. MEInvApprox) to a block of node-major vectors.
 //
-// With T = [[I, -C^T], [0, I]] the apply of Y = H^E X runs as
-//   pre        Xh = s X^C - C^T X^E,  Y^C = B^T X^E       (node-major lists)
-//   project    W  = D (P^C Xh + P^phi X^E)                 (projector rows)
-//   cell       Y^C += sum_c P_c^T H_c P_c Xh               (MFMA cell GEMM,
-//              eight colour passes, no two cells of a pass share a node)
-//   expand     Y^C += P^C^T W
-//   enrichment Y^E  = H^phiphi X^E + P^phi^T W + B Xh - C Y^C
+// T = [[I, -C^T], [0, I]] is applied when the operator is built: per cell the
+// coupling of the orthogonalized basis E_c = B_c - C_c H_c, the enrichment
+// block H^E_ee = H^phiphi - C B^T - E C^T and the projector rows
+// P~^phi = P^phi - P^C C^T are formed in FP64 (setup.hip).  The apply of
+// Y = alpha H^E X (+ the terms of the Chebyshev recurrence) then runs as
+//   project    W   = D (P^C s X^C + P~^phi X^E)
+//   init       Y^C = alpha P^C^T W + beta Z1 + gamma Z2 + alpha G Cl
+//   cell       Y^C += alpha sum_c P_c^T [H_c | E_c^T] [s X^C_c ; X^E_c]
+//              Yp_c = E_c s X^C_c       (MFMA cell GEMM, eight colour passes,
+//                                        no two cells of a pass share a node)
+//   reduce     Y^E = alpha (sum_c Yp_c + H^E_ee X^E + P~^phi^T W) + ...
 // where s = 1, or 1/m when the caller folds the CFE part of (M~^E)^-1 in.
 #include <algorithm>
 
@@ -151,6 +155,26 @@ struct CellMfma<float> {
   __device__ static inline int row(int v, int lk) { return 4 * lk + v; }
 };
 
+template <typename T>
+struct CellOps {
+  int ncells, nparts_c, nparts_e;
+  const int32_t *cells, *c2g;
+  int nloc, RB, KS, nf, ncols;
+  const T *Ht, *Et, *Ee;           // cell Hamiltonians, E_c^T and E_c tiles
+  const double *X;                 // CFE rows (even ld, 16-byte aligned)
+  int64_t ldx;
+  const double *scale, *minv;      // row scale of X (NULL: 1), 1/m (0 on the boundary)
+  const double *XE;                // enrichment rows
+  int64_t lde;
+  double *Y;                       // CFE rows, read-modify-write
+  int64_t ldy;
+  double alpha;
+  double *Yp;                      // enrichment partial rows, one row block per (cell, atom)
+  int64_t ldp;
+  const int32_t *cell_eptr, *cell_epair, *pair_atom;
+  const int64_t *cell_noff;
+};
+
 // waves per SIMD the wide tiles are compiled for: the FP64 accumulators of
 // one row block x ten column blocks leave room for three, the FP32 ones for four
 template <typename T, int CBM>
@@ -158,33 +182,74 @@ constexpr int cell_waves() {
   return CBM == 1 ? 1 : (sizeof(T) == 8 ? 3 : 4);
 }
 
-template <typename T, int RBW, int CBM>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(cell_waves<T, CBM>()))) void k_cell2(int ncells, int nparts,
-                                               const int32_t *__restrict__ cells,
-                                               const int32_t *__restrict__ c2g, int nloc, int RB,
-                                               int KS, const T *__restrict__ Ht,
-                                               const double *__restrict__ Xh, int64_t ldx,
-                                               double *__restrict__ Y, int64_t ldy,
-                                               const double *__restrict__ minv, int ncols) {
+// Cell GEMM of one colour pass of H^E = T^T Hhat T written per cell in the
+// orthogonalized basis: with X_c = [s X^C_c ; X^E_c] (the cell's nodes, scaled
+// by s, then the rows of its enrichment atoms),
+//   Y^C_c += alpha [H_c | E_c^T] X_c          (parts 0 .. nparts_c - 1)
+//   Yp_c   = E_c (s X^C_c)                      (parts nparts_c ..: the cell's
+//                                               enrichment rows, summed over
+//                                               cells afterwards)
+// One work-group = one cell of the colour and a part of its row blocks, all
+// (up to 160) columns.  Each wave keeps RBW row blocks x CBM column blocks of
+// accumulators, so every matrix fragment loaded from memory feeds CBM MFMAs.
+// The gathered rows stream through LDS in 16-row chunks, double buffered; the
+// matrix fragments of the next chunk are loaded into registers while the
+// current chunk is multiplied.  T = double (v_mfma_f64_16x16x4) or float
+// (v_mfma_f32_16x16x4, FP32 accumulation).  ENR = false: plain CFE.
+template <typename T, int RBW, int CBM, bool ENR>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(cell_waves<T, CBM>())))
+void k_cell3(CellOps<T> a) {
   typedef CellMfma<T> M;
   typedef typename M::acc_t acc_t;
-  constexpr int NC = CBM * 16, KC = 16, EPT = KC * NC / 256;
+  constexpr int NC = CBM * 16, KC = 16;
   __shared__ T Xs[2][KC][M::ncp(NC)];
-  __shared__ int32_t gs[EFE_MAXLOC];   // the cell's node numbers
+  // rows of the gathered block: the cell's nodes (CFE chunks, with their row
+  // scales), then the rows of its enrichment atoms (padding rows read row 0:
+  // the E_c^T tiles are zero in their columns)
+  __shared__ int32_t gs[16 * ((EFE_MAXLOC + 15) / 16) + (ENR ? EFE_MAX_CELL_ENR : 0)];
+  __shared__ double gsc[16 * ((EFE_MAXLOC + 15) / 16)];
   const int b = blockIdx.x;
+  const int nparts = a.nparts_c + a.nparts_e;
   const int xcd = b % 8, slot = b / 8;
   const int ci = (slot / nparts) * 8 + xcd;
   const int part = slot % nparts;
-  if (ci >= ncells) return;
-  const int cell = cells[ci];
-  const int32_t *g = c2g + (int64_t)cell * nloc;
+  if (ci >= a.ncells) return;
+  const int cell = a.cells[ci];
+  const int nloc = a.nloc, ncols = a.ncols;
   const int t = threadIdx.x, wave = t / 64, lane = t % 64, li = lane % 16, lk = lane / 16;
-  for (int l = t; l < nloc; l += 256) gs[l] = g[l];
+  const bool erole = part >= a.nparts_c;
+  int ne = 0, nep = 0;
+  int32_t p0 = 0;
+  int64_t noff = 0;
+  if (ENR) {
+    p0 = a.cell_eptr[cell];
+    ne = (a.cell_eptr[cell + 1] - p0) * a.nf;
+    nep = (ne + 15) / 16 * 16;
+    noff = a.cell_noff[cell];
+  }
+  const int RBE = nep / 16;
+  // enrichment-row parts beyond the cell's rows (uniform over the work-group)
+  if (erole && (!ENR || (part - a.nparts_c) * 4 * RBW >= RBE)) return;
+  const int NCHc = (a.KS + 3) / 4;
+  const int KCF = NCHc * 16;                 // CFE rows of the gathered block, padded
+  const int32_t *g = a.c2g + (int64_t)cell * nloc;
+  for (int l = t; l < KCF; l += 256) {
+    const int32_t node = g[min(l, nloc - 1)];
+    gs[l] = node;
+    gsc[l] = (l >= nloc || a.minv[node] == 0.0) ? 0.0 : (a.scale ? a.scale[node] : 1.0);
+  }
+  if (ENR && !erole)
+    for (int r = t; r < nep; r += 256)
+      gs[KCF + r] = r < ne ? a.pair_atom[a.cell_epair[p0 + r / a.nf]] * a.nf + r % a.nf : 0;
   __syncthreads();
-  const int rbase = (part * 4 + wave) * RBW;
+  const int nrb = erole ? RBE : a.RB;
+  const int rbase = ((erole ? part - a.nparts_c : part) * 4 + wave) * RBW;
   const int CB = (ncols + 15) / 16;
-  const int NCH = (KS + 3) / 4;
-  const T *hp = Ht + ((int64_t)cell * RB) * KS * 64 + lane;
+  const int NCH = NCHc + ((ENR && !erole) ? RBE : 0);
+  const int kse_n = nep / 4;
+  const T *hp = erole ? a.Ee + 4 * (int64_t)a.KS * noff + lane
+                      : a.Ht + ((int64_t)cell * a.RB) * a.KS * 64 + lane;
+  const T *tp = ENR ? a.Et + 16 * (int64_t)a.RB * noff + lane : hp;
 
   T a0[4][RBW], a1[4][RBW];
   acc_t acc[RBW][CBM];
@@ -196,52 +261,63 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(cell_waves<
   // Loads are unconditional, at clamped addresses, and nothing consumes a
   // loaded value before it is needed, so the compiler waits only for the
   // current chunk's operands and the next chunk's loads stay in flight.
-  // Out-of-range X rows and columns are zeroed when they are written to LDS;
-  // a clamped A fragment then multiplies zero rows of Xs (k past the end) or
-  // feeds accumulators that are never stored (row blocks past the end).
-  // wide tiles read the gathered rows as pairs of doubles (ldx even, so the
-  // pairs never cross a row) with 32-bit element offsets (the host checks
-  // n_nodes * ldx < 2^31)
+  // Out-of-range rows and columns are zeroed when they are written to LDS
+  // (row scale 0); a clamped A fragment then multiplies zero rows of Xs (k
+  // past the end) or feeds accumulators that are never stored (row blocks
+  // past the end).  Wide tiles read the rows as pairs of doubles with 32-bit
+  // element offsets (even leading dimensions; the host checks the offsets fit).
   constexpr bool PAIRS = NC >= 32;
-  constexpr int NP = PAIRS ? NC / 2 : NC, EPT2 = PAIRS ? KC * NP / 256 : EPT;
+  constexpr int NP = PAIRS ? NC / 2 : NC, EPT2 = KC * NP / 256;
   static_assert(KC * NP % 256 == 0, "the gather must cover the chunk exactly");
   const int NPV = (ncols + 1) / 2;
   double2 xr[EPT2];
+  // chunk ch reads rows ch*16 .. of the gathered block: CFE rows from X,
+  // enrichment rows from XE (a uniform choice per chunk)
   auto stage_load = [&](int ch) {
+    const bool ce = ENR && ch >= NCHc;
+    const double *base = ce ? a.XE : a.X;
+    const uint32_t ld = (uint32_t)(ce ? a.lde : a.ldx);
 #pragma unroll
     for (int j = 0; j < EPT2; ++j) {
-      const int idx = t + 256 * j, r = idx / NP, cp = idx % NP, k = ch * KC + r;
+      const int idx = t + 256 * j, r = idx / NP, cp = idx % NP;
+      const uint32_t row = (uint32_t)gs[ch * KC + r];
       if constexpr (PAIRS) {
-        const uint32_t off = (uint32_t)gs[min(k, nloc - 1)] * (uint32_t)ldx +
-                             2u * (uint32_t)min(cp, NPV - 1);
-        xr[j] = *reinterpret_cast<const double2 *>(Xh + off);
+        xr[j] = *reinterpret_cast<const double2 *>(base + row * ld +
+                                                   2u * (uint32_t)min(cp, NPV - 1));
       } else {
-        xr[j].x = Xh[(int64_t)gs[min(k, nloc - 1)] * ldx + min(cp, ncols - 1)];
+        xr[j].x = base[(int64_t)row * ld + min(cp, ncols - 1)];
       }
     }
   };
   auto stage_store = [&](int buf, int ch) {
+    const bool ce = ENR && ch >= NCHc;
 #pragma unroll
     for (int j = 0; j < EPT2; ++j) {
-      const int idx = t + 256 * j, r = idx / NP, cp = idx % NP, k = ch * KC + r;
-      const bool kr = k < nloc;
+      const int idx = t + 256 * j, r = idx / NP, cp = idx % NP;
+      const double s = ce ? 1.0 : gsc[ch * KC + r];
       if constexpr (PAIRS) {
-        Xs[buf][r][2 * cp] = (kr && 2 * cp < ncols) ? (T)xr[j].x : (T)0;
-        Xs[buf][r][2 * cp + 1] = (kr && 2 * cp + 1 < ncols) ? (T)xr[j].y : (T)0;
+        Xs[buf][r][2 * cp] = 2 * cp < ncols ? (T)(s * xr[j].x) : (T)0;
+        Xs[buf][r][2 * cp + 1] = 2 * cp + 1 < ncols ? (T)(s * xr[j].y) : (T)0;
       } else {
-        Xs[buf][r][cp] = (kr && cp < ncols) ? (T)xr[j].x : (T)0;
+        Xs[buf][r][cp] = cp < ncols ? (T)(s * xr[j].x) : (T)0;
       }
     }
   };
+  // A fragments of chunk ch: cell Hamiltonian (or E_c) tiles, then E_c^T tiles
   auto a_load = [&](int ch, T (&dst)[4][RBW]) {
+    const bool ce = ENR && ch >= NCHc;
+    const T *ap = ce ? tp : hp;
+    const int64_t rs = ce ? kse_n : a.KS;
+    const int k0 = ce ? (ch - NCHc) * 4 : ch * 4;
+    const int kmax = ce ? kse_n - 1 : a.KS - 1;
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
-      for (int r = 0; r < RBW; ++r)
-        dst[s][r] = hp[((int64_t)min(rbase + r, RB - 1) * KS + min(ch * 4 + s, KS - 1)) * 64];
+      for (int r = 0; r < RBW; ++r) {
+        const int64_t rb = min(rbase + r, nrb - 1);
+        dst[s][r] = ap[(rb * rs + min(k0 + s, kmax)) * 64];
+      }
   };
-  // k steps past the end meet zero rows of Xs and zero A fragments, and
-  // column blocks past the end zero columns: all MFMAs run unconditionally
   auto compute = [&](int buf, const T (&src)[4][RBW]) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
@@ -273,12 +349,32 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(cell_waves<
     step(ch, a0, a1, 0);
     if (ch + 1 < NCH) step(ch + 1, a1, a0, 1);
   }
+  if (erole) {
+    // the cell's enrichment rows: partial sums of E_c (s X^C_c)
+#pragma unroll
+    for (int r = 0; r < RBW; ++r) {
+      const int rb = rbase + r;
+      if (rb >= RBE) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int e = rb * 16 + M::row(v, lk);
+        if (e >= ne) continue;
+        double *yp = a.Yp + ((int64_t)a.nf * p0 + e) * a.ldp;
+#pragma unroll
+        for (int cb = 0; cb < CBM; ++cb) {
+          const int col = cb * 16 + li;
+          if (cb < CB && col < ncols) yp[col] = (double)acc[r][cb][v];
+        }
+      }
+    }
+    return;
+  }
   // scatter: per row block, all reads of Y first, then all writes, so the
   // reads overlap instead of each waiting for the one before
 #pragma unroll
   for (int r = 0; r < RBW; ++r) {
     const int rb = rbase + r;
-    if (rb >= RB) continue;
+    if (rb >= a.RB) continue;
     int64_t node[4];
     bool ok[4];
 #pragma unroll
@@ -288,16 +384,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(cell_waves<
       ok[v] = row < nloc;
     }
 #pragma unroll
-    for (int v = 0; v < 4; ++v) ok[v] = ok[v] && minv[node[v]] != 0.0;
+    for (int v = 0; v < 4; ++v) ok[v] = ok[v] && a.minv[node[v]] != 0.0;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       double yv[CBM];
 #pragma unroll
-      for (int cb = 0; cb < CBM; ++cb) yv[cb] = Y[node[v] * ldy + min(cb * 16 + li, ncols - 1)];
+      for (int cb = 0; cb < CBM; ++cb)
+        yv[cb] = a.Y[node[v] * a.ldy + min(cb * 16 + li, ncols - 1)];
 #pragma unroll
       for (int cb = 0; cb < CBM; ++cb) {
         const int col = cb * 16 + li;
-        if (ok[v] && cb < CB && col < ncols) Y[node[v] * ldy + col] = yv[cb] + (double)acc[r][cb][v];
+        if (ok[v] && cb < CB && col < ncols)
+          a.Y[node[v] * a.ldy + col] = yv[cb] + a.alpha * (double)acc[r][cb][v];
       }
     }
   }
@@ -317,8 +415,10 @@ __global__ __launch_bounds__(256) void k_cell_bf16(int ncells, int ntiles,
                                                    const int32_t *__restrict__ c2g, int nloc,
                                                    int RB, int KS32, const v8bf *__restrict__ Ht,
                                                    const double *__restrict__ Xh, int64_t ldx,
+                                                   const double *__restrict__ scale,
                                                    double *__restrict__ Y, int64_t ldy,
-                                                   const double *__restrict__ minv, int ncols) {
+                                                   const double *__restrict__ minv, int ncols,
+                                                   double alpha) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int KP = KS32 * 32;
   const int SK = KP + 8;                   // row stride of XT in bf16 elements
@@ -334,7 +434,11 @@ __global__ __launch_bounds__(256) void k_cell_bf16(int ncells, int ntiles,
   for (int idx = threadIdx.x; idx < KP * NT; idx += 256) {
     const int r = idx / NT, cc = idx % NT;
     double v = 0.0;
-    if (r < nloc && col0 + cc < ncols) v = Xh[(int64_t)g[r] * ldx + col0 + cc];
+    if (r < nloc && col0 + cc < ncols) {
+      const int64_t node = g[r];
+      const double s = minv[node] == 0.0 ? 0.0 : (scale ? scale[node] : 1.0);
+      v = s * Xh[node * ldx + col0 + cc];
+    }
     XT[cc * SK + r] = to_bf16(v);
   }
   __syncthreads();
@@ -360,22 +464,29 @@ __global__ __launch_bounds__(256) void k_cell_bf16(int ncells, int ntiles,
 #pragma unroll
       for (int cb = 0; cb < NT / 16; ++cb) {
         const int col = col0 + cb * 16 + li;
-        if (col < ncols) Y[node * ldy + col] += (double)acc[cb][v];
+        if (col < ncols) Y[node * ldy + col] += alpha * (double)acc[cb][v];
       }
     }
   }
 }
 
+
+// Affine epilogue of an apply (device copy of ApplyEpilogue)
+struct EpiArgs {
+  double alpha, beta, gamma;
+  const double *Z1, *Z2, *G, *Cl;
+};
 // ------------------------------------------------------------------ projectors
-// W[I] += D_I sum_s P^C_s Xh[node_s] over one work item (atom, support-list
-// range); the items of a node region run back to back, so the rows of Xh
-// they read are shared through the caches.  Waves take one support node at a
-// time (wave-uniform) for up to 192 columns, three per lane.
+// W[I] += D_I sum_s P^C_s s_node X[node_s] over one work item (atom, support-list
+// range); the items of a node region run back to back, so the rows of X they
+// read are shared through the caches.  Waves take one support node at a time
+// (wave-uniform) for up to 192 columns, three per lane.
 __global__ __launch_bounds__(256) void k_kb_project(int ncols, const int32_t *__restrict__ items,
                                                     XcdSplit xs,
                                                     const int32_t *__restrict__ kbnode,
                                                     const double *__restrict__ Pc,
-                                                    const double *__restrict__ Xh, int64_t ldh,
+                                                    const double *__restrict__ X, int64_t ldx,
+                                                    const double *__restrict__ scale,
                                                     const double *__restrict__ D,
                                                     double *__restrict__ W) {
   __shared__ double red[3][64 * POST_Q];
@@ -387,21 +498,22 @@ __global__ __launch_bounds__(256) void k_kb_project(int ncols, const int32_t *__
   const int lane = threadIdx.x % 64;
   const int c0 = blockIdx.y * 64 * POST_Q;
   double acc[POST_Q] = {0.0, 0.0, 0.0};
-  // entries it[1] + wave + 4 i: node numbers and coefficients come in 64 at
-  // a time by vector loads and reach the wave by readlane; clamped columns
-  // keep the row loads unconditional (their sums are not stored)
+  // entries it[1] + wave + 4 i: node numbers and coefficients (times the row
+  // scale) come in 64 at a time by vector loads and reach the wave by
+  // readlane; clamped columns keep the row loads unconditional (their sums
+  // are not stored)
   const int32_t s0 = it[1], s1 = it[2];
   for (int32_t sb = s0 + wave; sb < s1; sb += 256) {
     const int cnt = min(64, (s1 - sb + 3) / 4);
     const int32_t sl = min(sb + 4 * lane, s1 - 1);
     const int32_t nodes = kbnode[sl];
-    const double pv = Pc[sl];
+    const double pv = Pc[sl] * (scale ? scale[nodes] : 1.0);
     for (int i = 0; i < cnt; ++i) {
       const int64_t node = __builtin_amdgcn_readlane(nodes, i);
       const double p = lane_bcast(pv, i);
 #pragma unroll
       for (int q = 0; q < POST_Q; ++q)
-        acc[q] += p * Xh[node * ldh + min(c0 + 64 * q + lane, ncols - 1)];
+        acc[q] += p * X[node * ldx + min(c0 + 64 * q + lane, ncols - 1)];
     }
   }
   if (wave > 0)
@@ -419,9 +531,39 @@ __global__ __launch_bounds__(256) void k_kb_project(int ncols, const int32_t *__
     }
 }
 
-// W[I] = D_I sum_f P^phi_If XE_f (first term of the projector coefficients):
-// one work-group per (projector, 64 columns); the four waves take every
-// fourth f and their sums meet in LDS in a fixed order
+// sum of x over the work-group (256 threads), in a fixed order
+__device__ inline double block_sum256(double x, double *red) {
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+  if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = x;
+  __syncthreads();
+  const double t = (red[0] + red[1]) + (red[2] + red[3]);
+  __syncthreads();
+  return t;
+}
+
+// the same for one column: threads over the item's entries
+__global__ __launch_bounds__(256) void k_kb_project1(const int32_t *__restrict__ items,
+                                                     const int32_t *__restrict__ kbnode,
+                                                     const double *__restrict__ Pc,
+                                                     const double *__restrict__ X, int64_t ldx,
+                                                     const double *__restrict__ scale,
+                                                     const double *__restrict__ D,
+                                                     double *__restrict__ W) {
+  __shared__ double red[4];
+  const int32_t *it = items + 3 * (int64_t)blockIdx.x;
+  const int I = it[0];
+  double acc = 0.0;
+  for (int32_t s = it[1] + threadIdx.x; s < it[2]; s += 256) {
+    const int64_t node = kbnode[s];
+    acc += Pc[s] * (scale ? scale[node] : 1.0) * X[node * ldx];
+  }
+  const double t = block_sum256(acc, red);
+  if (threadIdx.x == 0) atomicAdd(&W[I], D[I] * t);
+}
+
+// W[I] = D_I sum_f P~^phi_If XE_f (the enrichment part of the projector
+// coefficients): one work-group per (projector, 64 columns); the four waves
+// take every fourth f and their sums meet in LDS in a fixed order
 __global__ __launch_bounds__(256) void k_kb_w_pphi(int ncols, int64_t n_enr,
                                                    const double *__restrict__ Pphi,
                                                    const double *__restrict__ XE, int64_t lde,
@@ -441,237 +583,87 @@ __global__ __launch_bounds__(256) void k_kb_w_pphi(int ncols, int64_t n_enr,
     W[(int64_t)I * ncols + col] = D[I] * (((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane]);
 }
 
-// Y^C[node] += sum_e P^C_e W[atom_e] over the node's projector entries.  One
-// wave per 8 consecutive nodes, three columns per lane.  The nodes' entry
-// pointers and (when the group has at most 64 entries, as usual) their
-// entries, contiguous for consecutive nodes, come in by vector loads and
-// reach the wave by readlane.
-__global__ __launch_bounds__(256) void k_kb_expand(int64_t n_nodes, int ncols,
-                                                   const int32_t *__restrict__ kbnm_ptr,
-                                                   const int32_t *__restrict__ kbnm_atom,
-                                                   const double *__restrict__ Pc_nm,
-                                                   const double *__restrict__ W,
-                                                   double *__restrict__ Y, int64_t ldy) {
+// Affine epilogue terms of one element: beta Z1 + gamma Z2 + alpha G Cl
+__device__ inline double epi_terms(const EpiArgs &e, int64_t o, int col) {
+  double v = 0.0;
+  if (e.Z1) v += e.beta * e.Z1[o];
+  if (e.Z2) v += e.gamma * e.Z2[o];
+  if (e.G) v += e.alpha * e.G[o] * e.Cl[col];
+  return v;
+}
+
+// Y^C[node] = alpha sum_e P^C_e W[atom_e] + epilogue terms on every interior
+// node (boundary rows 0): the projector expansion, and the start value of the
+// colour passes' read-modify-write.  One wave per 8 consecutive nodes, three
+// columns per lane.  The nodes' entry pointers and (when the group has at most
+// 64 entries, as usual) their entries come in by vector loads and reach the
+// wave by readlane.
+__global__ __launch_bounds__(256) void k_expand_init(int64_t n_nodes, int ncols,
+                                                     const int32_t *__restrict__ kbnm_ptr,
+                                                     const int32_t *__restrict__ kbnm_atom,
+                                                     const double *__restrict__ Pc_nm,
+                                                     const double *__restrict__ W,
+                                                     const double *__restrict__ minv,
+                                                     EpiArgs e, double *Y, int64_t ldy) {
   const int64_t grp =
       (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
   const int64_t n0 = grp * 8;
   if (n0 >= n_nodes) return;
   const int lane = threadIdx.x % 64;
   const int nn = (int)min<int64_t>(8, n_nodes - n0);
-  const int32_t pv = kbnm_ptr[n0 + min(lane, nn)];   // pointers of nodes n0 .. n0 + nn
+  const int32_t pv = kbnm_ptr ? kbnm_ptr[n0 + min(lane, nn)] : 0;
   const int32_t eb = __builtin_amdgcn_readlane(pv, 0), ee = __builtin_amdgcn_readlane(pv, nn);
-  if (eb == ee) return;
   const bool vec = ee - eb <= 64;
-  const int32_t el = min(eb + lane, ee - 1);
-  const int32_t av = kbnm_atom[el];
-  const double cv = Pc_nm[el];
+  const int32_t el = min(eb + lane, max(ee - 1, eb));
+  const int32_t av = ee > eb ? kbnm_atom[el] : 0;
+  const double cv = ee > eb ? Pc_nm[el] : 0.0;
   for (int c0 = 0; c0 < ncols; c0 += 64 * POST_Q) {
     for (int j = 0; j < nn; ++j) {
       const int32_t e0 = __builtin_amdgcn_readlane(pv, j);
       const int32_t e1 = __builtin_amdgcn_readlane(pv, j + 1);
-      if (e0 == e1) continue;
       double acc[POST_Q] = {0.0, 0.0, 0.0};
-      for (int32_t e = e0; e < e1; ++e) {
-        const int32_t atom = vec ? __builtin_amdgcn_readlane(av, e - eb) : kbnm_atom[e];
-        const double p = vec ? lane_bcast(cv, e - eb) : Pc_nm[e];
+      for (int32_t en = e0; en < e1; ++en) {
+        const int32_t atom = vec ? __builtin_amdgcn_readlane(av, en - eb) : kbnm_atom[en];
+        const double p = vec ? lane_bcast(cv, en - eb) : Pc_nm[en];
         const double *w = W + (int64_t)atom * ncols;
 #pragma unroll
         for (int q = 0; q < POST_Q; ++q) acc[q] += p * w[min(c0 + 64 * q + lane, ncols - 1)];
       }
-      double *y = Y + (n0 + j) * ldy;
+      const int64_t node = n0 + j;
+      const bool inner = minv[node] != 0.0;
 #pragma unroll
       for (int q = 0; q < POST_Q; ++q) {
         const int col = c0 + 64 * q + lane;
-        if (col < ncols) y[col] += acc[q];
+        if (col >= ncols) continue;
+        const int64_t o = node * ldy + col;
+        const double v = e.alpha * acc[q] + epi_terms(e, o, col);
+        Y[o] = inner ? v : 0.0;
       }
     }
   }
 }
 
-// Y^E[I] += sum_s (B_s Xh[node_s] - C_s Y[node_s]) over one work item
-// (atom I, range of its support list).  Each wave takes one support node at a
-// time (wave-uniform, so the 2 x nf coefficients come through the scalar
-// cache) for up to 192 columns, three per lane; the four waves' sums meet in
-// LDS and are added to Y^E once per item.
-__global__ __launch_bounds__(256) void k_enr_post(int nf, int ncols,
-                                                  const int32_t *__restrict__ items, XcdSplit xs,
-                                                  const int32_t *__restrict__ snode,
-                                                  const double *__restrict__ B_am,
-                                                  const double *__restrict__ C_am,
-                                                  const double *__restrict__ Xh, int64_t ldh,
-                                                  const double *__restrict__ Y, int64_t ldy,
-                                                  double *__restrict__ YE, int64_t lde) {
-  __shared__ double red[3][9][64 * POST_Q];
-  const int64_t item = xcd_block(xs);
-  if (item < 0) return;
-  const int32_t *it = items + 3 * item;
-  const int I = it[0];
-  const int32_t s0 = it[1], s1 = it[2];
-  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
-  const int lane = threadIdx.x % 64;
-  const int c0 = blockIdx.y * 64 * POST_Q;
-  double acc[POST_Q][9];
-#pragma unroll
-  for (int q = 0; q < POST_Q; ++q)
-#pragma unroll
-    for (int k = 0; k < 9; ++k) acc[q][k] = 0.0;
-  // This wave takes support entries s0 + wave + 4 i.  Their node numbers
-  // come in 64 at a time by one vector load, and the 2 nf coefficients of an
-  // entry by one vector load (lane k: B_k, lane 16 + k: C_k) one entry ahead
-  // of their use; readlane hands both to the wave.  Columns are clamped, so
-  // every load is unconditional; the sums of clamped columns are not stored.
-  const int kl = lane & 15;
-  const double *csrc = lane < 16 ? B_am : C_am;
-  auto cload = [&](int32_t s) -> double {
-    return csrc[(int64_t)min(s, s1 - 1) * nf + min(kl, nf - 1)];
-  };
-  for (int32_t sb = s0 + wave; sb < s1; sb += 256) {
-    const int cnt = min(64, (s1 - sb + 3) / 4);
-    const int32_t nodes = snode[min(sb + 4 * lane, s1 - 1)];
-    double cv = cload(sb);
-    for (int i = 0; i < cnt; ++i) {
-      const int32_t s = sb + 4 * i;
-      const int64_t node = __builtin_amdgcn_readlane(nodes, i);
-      const double cn = cload(s + 4);
-      double xh[POST_Q], y[POST_Q];
-#pragma unroll
-      for (int q = 0; q < POST_Q; ++q) {
-        const int col = min(c0 + 64 * q + lane, ncols - 1);
-        xh[q] = Xh[node * ldh + col];
-        y[q] = Y[node * ldy + col];
-      }
-#pragma unroll
-      for (int k = 0; k < 9; ++k) {
-        const double b = k < nf ? lane_bcast(cv, k) : 0.0;
-        const double c = k < nf ? lane_bcast(cv, 16 + k) : 0.0;
-#pragma unroll
-        for (int q = 0; q < POST_Q; ++q) acc[q][k] += b * xh[q] - c * y[q];
-      }
-      cv = cn;
-    }
-  }
-  if (wave > 0)
-#pragma unroll
-    for (int q = 0; q < POST_Q; ++q)
-#pragma unroll
-      for (int k = 0; k < 9; ++k) red[wave - 1][k][64 * q + lane] = acc[q][k];
-  __syncthreads();
-  if (wave == 0) {
-#pragma unroll
-    for (int q = 0; q < POST_Q; ++q) {
-      const int col = c0 + 64 * q + lane;
-      if (col >= ncols) continue;
-#pragma unroll
-      for (int k = 0; k < 9; ++k) {
-        const double v = acc[q][k] + red[0][k][64 * q + lane] + red[1][k][64 * q + lane] +
-                         red[2][k][64 * q + lane];
-        if (k < nf) atomicAdd(&YE[(int64_t)(I * nf + k) * lde + col], v);
-      }
-    }
-  }
-}
-
-// ------------------------------------------------------------- one column
-// Single-vector forms of the four row kernels (the Lanczos bound applies
-// H^E to one vector): threads run over nodes or support entries instead of
-// columns, so no lane idles.  Same sums, same order within each node.
-
-// sum of x over the work-group (256 threads), in a fixed order
-__device__ inline double block_sum256(double x, double *red) {
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-  if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = x;
-  __syncthreads();
-  const double t = (red[0] + red[1]) + (red[2] + red[3]);
-  __syncthreads();
-  return t;
-}
-
-__global__ __launch_bounds__(256) void k_pre1(int64_t n_nodes, const double *__restrict__ XC,
-                                              int64_t ldx, const double *__restrict__ scale,
-                                              const double *__restrict__ minv,
-                                              const double *__restrict__ XE, int64_t lde,
-                                              const int32_t *__restrict__ g_ptr,
-                                              const int32_t *__restrict__ g_atom,
-                                              const double *__restrict__ Cg,
-                                              const double *__restrict__ Bg, int nf,
-                                              double *__restrict__ Xh, int64_t ldh, double *Y,
-                                              int64_t ldy) {
-  const int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (n >= n_nodes) return;
-  const int64_t grp = n / 8;
-  const int j = (int)(n % 8);
-  const bool inner = minv[n] != 0.0;
-  double xh = inner ? (scale ? scale[n] : 1.0) * XC[n * ldx] : 0.0, y = 0.0;
-  for (int32_t a = g_ptr[grp]; a < g_ptr[grp + 1]; ++a) {
-    const double *xe = XE + (int64_t)g_atom[a] * nf * lde;
-    for (int k = 0; k < nf; ++k) {
-      const double v = xe[(int64_t)k * lde];
-      xh -= Cg[((int64_t)a * nf + k) * 8 + j] * v;
-      y += Bg[((int64_t)a * nf + k) * 8 + j] * v;
-    }
-  }
-  Xh[n * ldh] = inner ? xh : 0.0;
-  if (Y) Y[n * ldy] = inner ? y : 0.0;
-}
-
-// W[I] += D_I sum_s P^C_s Xh[node_s] over one work item, threads over entries
-__global__ __launch_bounds__(256) void k_kb_project1(const int32_t *__restrict__ items,
-                                                     const int32_t *__restrict__ kbnode,
-                                                     const double *__restrict__ Pc,
-                                                     const double *__restrict__ Xh, int64_t ldh,
-                                                     const double *__restrict__ D,
-                                                     double *__restrict__ W) {
-  __shared__ double red[4];
-  const int32_t *it = items + 3 * (int64_t)blockIdx.x;
-  const int I = it[0];
-  double acc = 0.0;
-  for (int32_t s = it[1] + threadIdx.x; s < it[2]; s += 256) acc += Pc[s] * Xh[(int64_t)kbnode[s] * ldh];
-  const double t = block_sum256(acc, red);
-  if (threadIdx.x == 0) atomicAdd(&W[I], D[I] * t);
-}
-
-// Y^C[node] += sum_e P^C_e W[atom_e], one thread per node
-__global__ __launch_bounds__(256) void k_kb_expand1(int64_t n_nodes,
-                                                    const int32_t *__restrict__ kbnm_ptr,
-                                                    const int32_t *__restrict__ kbnm_atom,
-                                                    const double *__restrict__ Pc_nm,
-                                                    const double *__restrict__ W,
-                                                    double *__restrict__ Y, int64_t ldy) {
-  const int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (n >= n_nodes) return;
-  const int32_t e0 = kbnm_ptr[n], e1 = kbnm_ptr[n + 1];
-  if (e0 == e1) return;
-  double acc = 0.0;
-  for (int32_t e = e0; e < e1; ++e) acc += Pc_nm[e] * W[kbnm_atom[e]];
-  Y[n * ldy] += acc;
-}
-
-// Y^E[I] += sum_s (B_s Xh[node_s] - C_s Y[node_s]) over one work item, threads
-// over entries, one work-group sum per enrichment function
-__global__ __launch_bounds__(256) void k_enr_post1(int nf, const int32_t *__restrict__ items,
-                                                   const int32_t *__restrict__ snode,
-                                                   const double *__restrict__ B_am,
-                                                   const double *__restrict__ C_am,
-                                                   const double *__restrict__ Xh, int64_t ldh,
-                                                   const double *__restrict__ Y, int64_t ldy,
-                                                   double *__restrict__ YE, int64_t lde) {
-  __shared__ double red[4];
-  const int32_t *it = items + 3 * (int64_t)blockIdx.x;
-  const int I = it[0];
-  const int32_t s0 = it[1], s1 = it[2];
-  double acc[16];
-#pragma unroll
-  for (int k = 0; k < 16; ++k) acc[k] = 0.0;
-  for (int32_t s = s0 + threadIdx.x; s < s1; s += 256) {
-    const int64_t node = snode[s];
-    const double x = Xh[node * ldh], y = Y[node * ldy];
-#pragma unroll
-    for (int k = 0; k < 16; ++k)
-      if (k < nf) acc[k] += B_am[(int64_t)s * nf + k] * x - C_am[(int64_t)s * nf + k] * y;
-  }
-  for (int k = 0; k < nf; ++k) {
-    const double t = block_sum256(acc[k], red);
-    if (threadIdx.x == 0) atomicAdd(&YE[(int64_t)(I * nf + k) * lde], t);
+// Y^E[I] = alpha (sum over the cells of atom I of their partial rows + TE[I])
+// + epilogue terms, the partial rows added in cell order (fixed).  One
+// work-group per (atom, 64 columns); the four waves take every fourth function.
+__global__ __launch_bounds__(256) void k_enr_reduce(int nf, int ncols,
+                                                    const int32_t *__restrict__ cpair_ptr,
+                                                    const int32_t *__restrict__ cpair_cpos,
+                                                    const double *__restrict__ Yp, int64_t ldp,
+                                                    const double *__restrict__ TE,
+                                                    EpiArgs e, double *YE, int64_t ldy) {
+  const int I = blockIdx.x;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int col = blockIdx.y * 64 + lane;
+  if (col >= ncols) return;
+  const int32_t q0 = cpair_ptr[I], q1 = cpair_ptr[I + 1];
+  for (int k = wave; k < nf; k += 4) {
+    double acc = 0.0;
+    for (int32_t q = q0; q < q1; ++q) acc += Yp[((int64_t)nf * cpair_cpos[q] + k) * ldp + col];
+    const int64_t f = (int64_t)I * nf + k;
+    acc += TE[f * ncols + col];
+    const int64_t o = f * ldy + col;
+    YE[o] = e.alpha * acc + epi_terms(e, o, col);
   }
 }
 
@@ -704,86 +696,157 @@ __global__ void k_enr_block_apply(int natoms, int nf, int ncols, const double *_
 // ------------------------------------------------------------------ launchers
 // Colour passes of the cell GEMM in column chunks of 16 CBM.
 template <typename T, int RBW, int CBM>
-static void launch_cell2(efe_ctx *c, const T *Ht, const double *Xh, int64_t ldh, double *Y,
-                         int64_t ldy, int ncols) {
-  const int nparts = (int)cdiv(c->RB, 4 * RBW);
+static void launch_cell3(efe_ctx *c, const T *Ht, const T *Et, const T *Ee, const double *X,
+                         int64_t ldx, const double *scale, const double *XE, int64_t lde,
+                         double *Y, int64_t ldy, double alpha, double *Yp, int64_t ldp,
+                         int ncols) {
+  const bool enr = c->n_enr > 0 && c->ncpairs > 0;
+  CellOps<T> a;
+  a.nparts_c = (int)cdiv(c->RB, 4 * RBW);
+  a.nparts_e = enr ? (int)cdiv(c->max_rbe, 4 * RBW) : 0;
+  a.c2g = c->d_c2g;
+  a.nloc = c->nloc;
+  a.RB = c->RB;
+  a.KS = c->KS;
+  a.nf = c->nf;
+  a.Ht = Ht;
+  a.Et = Et;
+  a.Ee = Ee;
+  a.ldx = ldx;
+  a.scale = scale;
+  a.minv = c->d_minv;
+  a.lde = lde;
+  a.ldy = ldy;
+  a.alpha = alpha;
+  a.ldp = ldp;
+  a.cell_eptr = c->d_cell_eptr;
+  a.cell_epair = c->d_cell_epair;
+  a.pair_atom = c->d_cpair_atom;
+  a.cell_noff = c->d_cell_noff;
+  const int nparts = a.nparts_c + a.nparts_e;
   for (int col0 = 0; col0 < ncols; col0 += 16 * CBM) {
-    const int nch = std::min(16 * CBM, ncols - col0);
+    a.ncols = std::min(16 * CBM, ncols - col0);
+    a.X = X + col0;
+    a.XE = XE + col0;
+    a.Y = Y + col0;
+    a.Yp = Yp + col0;
     for (int col = 0; col < 8; ++col) {
       const int nc = c->colour_offsets[col + 1] - c->colour_offsets[col];
       if (nc == 0) continue;
+      a.ncells = nc;
+      a.cells = c->d_colour_order + c->colour_offsets[col];
       const int64_t nblk = cdiv(nc, 8) * 8 * nparts;
       const int t = efe_timer_begin(c, CBM == 1 ? EFE_T_CELL_NARROW : EFE_T_CELL);
-      k_cell2<T, RBW, CBM><<<nblk, 256, 0, c->stream>>>(
-          nc, nparts, c->d_colour_order + c->colour_offsets[col], c->d_c2g, c->nloc, c->RB, c->KS,
-          Ht, Xh + col0, ldh, Y + col0, ldy, c->d_minv, nch);
+      if (enr)
+        k_cell3<T, RBW, CBM, true><<<nblk, 256, 0, c->stream>>>(a);
+      else
+        k_cell3<T, RBW, CBM, false><<<nblk, 256, 0, c->stream>>>(a);
       efe_timer_end(c, CBM == 1 ? EFE_T_CELL_NARROW : EFE_T_CELL, t);
     }
   }
 }
 
+__global__ void k_fill_zero(int64_t n, double *__restrict__ x) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) x[i] = 0.0;
+}
+
+// X -> Xc with an even leading dimension (the cell GEMM's paired gathers)
+__global__ void k_copy_cols(int64_t rows, int ncols, const double *__restrict__ X, int64_t ldx,
+                            double *__restrict__ Y, int64_t ldy) {
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= rows * ncols) return;
+  const int64_t r = idx / ncols;
+  const int j = (int)(idx % ncols);
+  Y[r * ldy + j] = X[r * ldx + j];
+}
+
 efe_status efe_apply_H_internal(efe_ctx *c, const double *XC, int64_t ldx, const double *scale,
                                 const double *XE, int64_t lde, double *Y, int64_t ldy, int ncols,
-                                int prec) {
+                                int prec, const ApplyEpilogue *epi) {
   if (!c->have_potential) EFE_FAIL(c, EFE_ESTATE, "no potential set");
   if (ncols <= 0) return EFE_OK;
+  if (ncols > EFE_COL_CHUNK) EFE_FAIL(c, EFE_EINVAL, "apply chunk wider than 160 columns");
   if ((prec == EFE_FP32 && !c->have32) || (prec == EFE_BF16 && !c->have16))
     EFE_FAIL(c, EFE_ESTATE, "reduced-precision cell matrices were not built by efe_set_potential");
+  if (prec == EFE_BF16 && c->n_enr > 0)
+    EFE_FAIL(c, EFE_EINVAL, "the BF16 cell GEMM takes plain CFE systems only");
   efe_status s;
-  double *Xh, *W = nullptr;
-  // even row length: the cell GEMM reads X^ in pairs of doubles
-  const int64_t ldh = (ncols + 1) & ~1;
-  if (c->nf > 16) EFE_FAIL(c, EFE_EINVAL, "more than 16 enrichment functions per atom");
-  if (c->n_nodes * ldh >= (1ll << 31))
-    EFE_FAIL(c, EFE_EINVAL, "n_nodes x columns exceeds the 32-bit offsets of the cell GEMM");
-  if ((s = efe_ws(c, 0, (size_t)c->n_nodes * ldh * 8, (void **)&Xh))) return s;
-  if (c->nproj && (s = efe_ws(c, 1, (size_t)c->nproj * ncols * 8, (void **)&W))) return s;
   const int nf = c->nf;
-  double *YE = Y + c->n_nodes * ldy;
+  const int64_t nn = c->n_nodes, ne = c->n_enr;
+  ApplyEpilogue E0;
+  const ApplyEpilogue &ep = epi ? *epi : E0;
+  // the cell GEMM reads the CFE rows in pairs with 32-bit offsets: other
+  // layouts are copied to an even leading dimension first
+  const bool pairs_ok = (ldx % 2 == 0) && ((uintptr_t)XC % 16 == 0) && nn * ldx < (1ll << 31);
+  if (!pairs_ok) {
+    const int64_t ldc = (ncols + 1) & ~1;
+    double *Xc;
+    if (nn * ldc >= (1ll << 31))
+      EFE_FAIL(c, EFE_EINVAL, "n_nodes x columns exceeds the 32-bit offsets of the cell GEMM");
+    if ((s = efe_ws(c, 0, (size_t)nn * ldc * 8, (void **)&Xc))) return s;
+    k_copy_cols<<<cdiv(nn * ncols, 256), 256, 0, c->stream>>>(nn, ncols, XC, ldx, Xc, ldc);
+    XC = Xc;
+    ldx = ldc;
+  }
+  if (ne && ((lde % 2) || ((uintptr_t)XE % 16) || ne * lde >= (1ll << 31))) {
+    const int64_t ldc = (ncols + 1) & ~1;
+    double *Xc;
+    if ((s = efe_ws(c, 12, (size_t)ne * ldc * 8, (void **)&Xc))) return s;
+    k_copy_cols<<<cdiv(ne * ncols, 256), 256, 0, c->stream>>>(ne, ncols, XE, lde, Xc, ldc);
+    XE = Xc;
+    lde = ldc;
+  }
+  double *W = nullptr, *Yp = nullptr, *TE = nullptr;
+  if (c->nproj && (s = efe_ws(c, 1, (size_t)c->nproj * ncols * 8, (void **)&W))) return s;
+  if (ne) {
+    if ((s = efe_ws(c, 9, (size_t)nf * std::max<int64_t>(c->ncpairs, 1) * ncols * 8, (void **)&Yp)))
+      return s;
+    if ((s = efe_ws(c, 11, (size_t)ne * ncols * 8, (void **)&TE))) return s;
+  }
+  EpiArgs ec{ep.alpha, ep.beta, ep.gamma, ep.Z1, ep.Z2, ep.G, ep.Cl};
   const int t_cls = ncols <= 16 ? EFE_T_APPLY_NARROW : EFE_T_APPLY;
   const int t_apply = efe_timer_begin(c, t_cls);
-  // pre: Xh and Y^C = B^T X^E
+  // 1. projector coefficients W = D (P^C s X^C + P~^phi X^E), then Y^C =
+  //    alpha P^C^T W + epilogue terms on every node
   {
     const int t = efe_timer_begin(c, EFE_T_PRE);
-    if (ncols == 1)
-      k_pre1<<<cdiv(c->n_nodes, 256), 256, 0, c->stream>>>(c->n_nodes, XC, ldx, scale, c->d_minv,
-                                                           XE, lde, c->d_g_ptr, c->d_g_atom,
-                                                           c->d_Cg, c->d_Bg, nf, Xh, ldh, Y, ldy);
-    else
-      k_pre<<<cdiv(c->n_nodes, 32), 256, 0, c->stream>>>(c->n_nodes, ncols, XC, ldx, scale,
-                                                         c->d_minv, XE, lde, c->d_g_ptr,
-                                                         c->d_g_atom, c->d_Cg, c->d_Bg, nf, Xh, ldh,
-                                                         Y, ldy);
+    if (c->nproj) {
+      // (without enrichment this writes W = 0)
+      k_kb_w_pphi<<<dim3(c->nproj, cdiv(ncols, 64)), 256, 0, c->stream>>>(
+          ncols, ne, c->d_Ptil, XE, lde, c->d_D, W);
+      if (c->n_kb_items) {
+        XcdSplit xs;
+        for (int i = 0; i <= 8; ++i) xs.off[i] = c->kb_items_off[i];
+        if (ncols == 1)
+          k_kb_project1<<<c->n_kb_items, 256, 0, c->stream>>>(c->d_kb_items, c->d_kbnode,
+                                                              c->d_Pc_am, XC, ldx, scale, c->d_D, W);
+        else
+          k_kb_project<<<dim3(8 * xs.max_len(), cdiv(ncols, 64 * POST_Q)), 256, 0, c->stream>>>(
+              ncols, c->d_kb_items, xs, c->d_kbnode, c->d_Pc_am, XC, ldx, scale, c->d_D, W);
+      }
+    }
+    k_expand_init<<<cdiv(nn, 32), 256, 0, c->stream>>>(
+        nn, ncols, c->nproj ? c->d_kbnm_ptr : nullptr, c->d_kbnm_atom, c->d_Pc_nm, W, c->d_minv,
+        ec, Y, ldy);
     efe_timer_end(c, EFE_T_PRE, t);
   }
-  // projector coefficients
-  if (c->nproj) {
-    k_kb_w_pphi<<<dim3(c->nproj, cdiv(ncols, 64)), 256, 0, c->stream>>>(ncols, c->n_enr, c->d_Pphi,
-                                                                        XE, lde, c->d_D, W);
-    if (c->n_kb_items) {
-      XcdSplit xs;
-      for (int i = 0; i <= 8; ++i) xs.off[i] = c->kb_items_off[i];
-      dim3 grd(8 * xs.max_len(), cdiv(ncols, 64 * POST_Q));
-      if (ncols == 1)
-        k_kb_project1<<<c->n_kb_items, 256, 0, c->stream>>>(c->d_kb_items, c->d_kbnode, c->d_Pc_am,
-                                                            Xh, ldh, c->d_D, W);
-      else
-        k_kb_project<<<grd, 256, 0, c->stream>>>(ncols, c->d_kb_items, xs, c->d_kbnode,
-                                                 c->d_Pc_am, Xh, ldh, c->d_D, W);
-    }
-  }
-  // cell GEMM, colour by colour
-  // 160-column register tiles; a single 16-column tile (six row blocks per
-  // wave, one part per cell) for narrow blocks such as the Lanczos vector
-  if (prec == EFE_FP64 && ncols <= 16) {
-    launch_cell2<double, 6, 1>(c, c->d_Htile64, Xh, ldh, Y, ldy, ncols);
-  } else if (prec == EFE_FP64) {
-    launch_cell2<double, 1, 10>(c, c->d_Htile64, Xh, ldh, Y, ldy, ncols);
-  } else if (prec == EFE_FP32 && ncols <= 16) {
-    launch_cell2<float, 6, 1>(c, c->d_Htile32, Xh, ldh, Y, ldy, ncols);
-  } else if (prec == EFE_FP32) {
-    launch_cell2<float, 1, 10>(c, c->d_Htile32, Xh, ldh, Y, ldy, ncols);
-  } else {
+  // 2. cell GEMM, colour by colour: 160-column register tiles; a single
+  //    16-column tile (six row blocks per wave) for narrow blocks such as the
+  //    Lanczos vector
+  if (prec == EFE_FP64 && ncols <= 16)
+    launch_cell3<double, 6, 1>(c, c->d_Htile64, c->d_Et64, c->d_Ee64, XC, ldx, scale, XE, lde, Y,
+                               ldy, ep.alpha, Yp, ncols, ncols);
+  else if (prec == EFE_FP64)
+    launch_cell3<double, 1, 10>(c, c->d_Htile64, c->d_Et64, c->d_Ee64, XC, ldx, scale, XE, lde, Y,
+                                ldy, ep.alpha, Yp, ncols, ncols);
+  else if (prec == EFE_FP32 && ncols <= 16)
+    launch_cell3<float, 6, 1>(c, c->d_Htile32, c->d_Et32, c->d_Ee32, XC, ldx, scale, XE, lde, Y,
+                              ldy, ep.alpha, Yp, ncols, ncols);
+  else if (prec == EFE_FP32)
+    launch_cell3<float, 1, 10>(c, c->d_Htile32, c->d_Et32, c->d_Ee32, XC, ldx, scale, XE, lde, Y,
+                               ldy, ep.alpha, Yp, ncols, ncols);
+  else {
     const int NT = 32;
     const int ntiles = (int)cdiv(ncols, NT);
     const size_t shm = (size_t)NT * (c->KS32 * 32 + 8) * 2;
@@ -793,42 +856,28 @@ efe_status efe_apply_H_internal(efe_ctx *c, const double *XC, int64_t ldx, const
       const int64_t nblk = cdiv(nc, 8) * 8 * ntiles;
       const int t = efe_timer_begin(c, EFE_T_CELL);
       k_cell_bf16<32><<<nblk, 256, shm, c->stream>>>(
-            nc, ntiles, c->d_colour_order + c->colour_offsets[col], c->d_c2g, c->nloc, c->RB,
-            c->KS32, (const v8bf *)c->d_Htile16, Xh, ldh, Y, ldy, c->d_minv, ncols);
+          nc, ntiles, c->d_colour_order + c->colour_offsets[col], c->d_c2g, c->nloc, c->RB,
+          c->KS32, (const v8bf *)c->d_Htile16, XC, ldx, scale, Y, ldy, c->d_minv, ncols,
+          ep.alpha);
       efe_timer_end(c, EFE_T_CELL, t);
     }
   }
-  if (c->nproj) {
-    if (ncols == 1)
-      k_kb_expand1<<<cdiv(c->n_nodes, 256), 256, 0, c->stream>>>(c->n_nodes, c->d_kbnm_ptr,
-                                                                 c->d_kbnm_atom, c->d_Pc_nm, W, Y,
-                                                                 ldy);
-    else
-      k_kb_expand<<<cdiv(c->n_nodes, 32), 256, 0, c->stream>>>(c->n_nodes, ncols, c->d_kbnm_ptr,
-                                                              c->d_kbnm_atom, c->d_Pc_nm, W, Y, ldy);
-  }
-  // enrichment rows
+  // 3. enrichment rows: Y^E = alpha (sum of the cells' partial rows
+  //    + H^E_ee X^E + P~^phi^T W) + epilogue terms
   const int t_post = efe_timer_begin(c, EFE_T_POST);
-  if (c->n_enr) {
-    if ((s = efe_gemm(c, false, false, c->n_enr, ncols, c->n_enr, 1.0, c->d_Hpp, c->n_enr, XE, lde,
-                      0.0, YE, ldy)))
+  if (ne) {
+    k_fill_zero<<<cdiv(ne * ncols, 256), 256, 0, c->stream>>>(ne * ncols, TE);
+    if ((s = efe_gemm_acc(c, false, ne, ncols, ne, 1.0, c->d_Hee, ne, XE, lde, TE, ncols)))
       return s;
     if (c->nproj &&
-        (s = efe_gemm(c, true, false, c->n_enr, ncols, c->nproj, 1.0, c->d_Pphi, c->n_enr, W, ncols,
-                      1.0, YE, ldy)))
+        (s = efe_gemm_acc(c, true, ne, ncols, c->nproj, 1.0, c->d_Ptil, ne, W, ncols, TE, ncols)))
       return s;
-    if (c->n_enr_items) {
-      XcdSplit xs;
-      for (int i = 0; i <= 8; ++i) xs.off[i] = c->enr_items_off[i];
-      dim3 grd(8 * xs.max_len(), cdiv(ncols, 64 * POST_Q));
-      if (ncols == 1)
-        k_enr_post1<<<c->n_enr_items, 256, 0, c->stream>>>(nf, c->d_enr_items, c->d_snode,
-                                                           c->d_B_am, c->d_C_am, Xh, ldh, Y, ldy,
-                                                           YE, ldy);
-      else
-        k_enr_post<<<grd, 256, 0, c->stream>>>(nf, ncols, c->d_enr_items, xs, c->d_snode,
-                                               c->d_B_am, c->d_C_am, Xh, ldh, Y, ldy, YE, ldy);
-    }
+    EpiArgs ee = ec;
+    if (ee.Z1) ee.Z1 += nn * ldy;
+    if (ee.Z2) ee.Z2 += nn * ldy;
+    if (ee.G) ee.G += nn * ldy;
+    k_enr_reduce<<<dim3(c->natoms, cdiv(ncols, 64)), 256, 0, c->stream>>>(
+        nf, ncols, c->d_cpair_ptr, c->d_cpair_cpos, Yp, ncols, TE, ee, Y + nn * ldy, ldy);
   }
   efe_timer_end(c, EFE_T_POST, t_post);
   efe_timer_end(c, t_cls, t_apply);

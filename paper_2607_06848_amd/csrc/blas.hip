@@ -1,9 +1,7 @@
-// FP64 dense products around the hot path: plain GEMMs (enrichment blocks,
-// subspace rotations) go to rocBLAS; a tiled kernel covers the weighted
-// products, and a split-K kernel the tall-skinny weighted Grams V^T M V of
-// Rayleigh-Ritz.
-#include <rocblas/rocblas.h>
-
+// FP64 dense products around the hot path: a tiled kernel for plain and
+// weighted products, split over the summation index (partial sums added
+// atomically) for the enrichment blocks of the apply and the tall-skinny
+// weighted Grams V^T M V of Rayleigh-Ritz.
 #include "efe_internal.h"
 
 // C = alpha op(A) op(B) (+ beta C), row-major, 64x64 tiles, 16-deep k steps;
@@ -83,22 +81,6 @@ efe_status efe_gemm(efe_ctx *ctx, bool ta, bool tb, int64_t M, int64_t N, int64_
   if (K <= 0) {
     EFE_FAIL(ctx, EFE_EINVAL, "efe_gemm with K = 0");
   }
-  if (!wK && M < (1ll << 31) && N < (1ll << 31) && K < (1ll << 31) && lda < (1ll << 31) &&
-      ldb < (1ll << 31) && ldc < (1ll << 31)) {
-    // plain products go to rocBLAS (FP64 MFMA) on the context's stream.  The
-    // row-major C = op(A) op(B) is the column-major C^T = op(B)^T op(A)^T, so
-    // the operands swap and each keeps its own transpose flag.
-    void *hv;
-    efe_status s;
-    if ((s = efe_blas_handle(ctx, &hv))) return s;
-    const rocblas_status st = rocblas_dgemm(
-        (rocblas_handle)hv, tb ? rocblas_operation_transpose : rocblas_operation_none,
-        ta ? rocblas_operation_transpose : rocblas_operation_none, (rocblas_int)N, (rocblas_int)M,
-        (rocblas_int)K, &alpha, B, (rocblas_int)ldb, A, (rocblas_int)lda, &beta, C,
-        (rocblas_int)ldc);
-    if (st != rocblas_status_success) EFE_FAIL(ctx, EFE_EHIP, "rocblas_dgemm failed");
-    return EFE_OK;
-  }
   dim3 grid(cdiv(N, 64), cdiv(M, 64), 1);
   if (grid.y > 65535u * 32u) EFE_FAIL(ctx, EFE_EINVAL, "gemm grid too large");
 #define GL(a, b) \
@@ -108,6 +90,27 @@ efe_status efe_gemm(efe_ctx *ctx, bool ta, bool tb, int64_t M, int64_t N, int64_
   else if (!ta && tb) GL(false, true);
   else GL(true, true);
 #undef GL
+  HIPCHK(ctx, hipGetLastError());
+  return EFE_OK;
+}
+
+efe_status efe_gemm_acc(efe_ctx *ctx, bool ta, int64_t M, int64_t N, int64_t K, double alpha,
+                        const double *A, int64_t lda, const double *B, int64_t ldb, double *C,
+                        int64_t ldc) {
+  if (M <= 0 || N <= 0 || K <= 0) return EFE_OK;
+  // split the sum over K so that the launch fills the chip; partial sums
+  // meet in C by atomic adds
+  const int64_t tiles = cdiv(M, 64) * cdiv(N, 64);
+  int64_t nsplit = std::max<int64_t>(1, cdiv(1024, tiles));
+  int64_t kchunk = std::max<int64_t>(64, cdiv(cdiv(K, nsplit), 16) * 16);
+  nsplit = cdiv(K, kchunk);
+  dim3 grid(cdiv(N, 64), cdiv(M, 64), nsplit);
+  if (ta)
+    k_gemm<true, false, true><<<grid, 256, 0, ctx->stream>>>(M, N, K, alpha, A, lda, B, ldb, 0.0,
+                                                             C, ldc, nullptr, kchunk);
+  else
+    k_gemm<false, false, true><<<grid, 256, 0, ctx->stream>>>(M, N, K, alpha, A, lda, B, ldb, 0.0,
+                                                              C, ldc, nullptr, kchunk);
   HIPCHK(ctx, hipGetLastError());
   return EFE_OK;
 }

@@ -360,6 +360,91 @@ extern "C" efe_status efe_setup_mesh(const efe_mesh_desc *mesh, const efe_system
       TRY(upload(c, &c->d_nm_gslot, gslot));
       HIPCHK(c, hipStreamSynchronize(c->stream));
     }
+    // coupling pairs: per atom every cell that holds one of its support nodes
+    // (its support cells and the layer of cells around them, where C is
+    // non-zero on shared nodes although phi vanishes), with the local-to-
+    // support map and the support pair of the cell (-1 for the outer layer);
+    // then their cell-major view (atom-major pairs are sorted by atom, so a
+    // cell's pairs come out in ascending atom order)
+    {
+      std::vector<int32_t> cptr(c->natoms + 1, 0), catom, ccell, cspair, clmap;
+      std::vector<int32_t> pos(c->n_nodes, -1), cmark(c->n_cells, -1);
+      const int64_t n1x = c->n1[0], n1y = c->n1[1];
+      for (int I = 0; I < c->natoms && c->nf > 0; ++I) {
+        std::vector<int32_t> cl;
+        for (int32_t sI = E.snode_ptr[I]; sI < E.snode_ptr[I + 1]; ++sI) {
+          const int64_t nd = E.snode[sI];
+          pos[nd] = sI;
+          const int64_t ijk[3] = {nd % n1x, (nd / n1x) % n1y, nd / (n1x * n1y)};
+          int cs[3][2], nc[3];
+          for (int d = 0; d < 3; ++d) {
+            const int cc = (int)(ijk[d] / c->p), aa = (int)(ijk[d] % c->p);
+            nc[d] = 0;
+            if (aa == 0 && cc > 0) cs[d][nc[d]++] = cc - 1;
+            if (cc < c->ncell[d]) cs[d][nc[d]++] = cc;
+          }
+          for (int z = 0; z < nc[2]; ++z)
+            for (int y = 0; y < nc[1]; ++y)
+              for (int x = 0; x < nc[0]; ++x) {
+                const int32_t cell =
+                    cs[0][x] + c->ncell[0] * (cs[1][y] + c->ncell[1] * cs[2][z]);
+                if (cmark[cell] != I) {
+                  cmark[cell] = I;
+                  cl.push_back(cell);
+                }
+              }
+        }
+        std::sort(cl.begin(), cl.end());
+        for (int32_t cell : cl) {
+          catom.push_back(I);
+          ccell.push_back(cell);
+          auto it = std::lower_bound(E.cells.begin() + E.ptr[I], E.cells.begin() + E.ptr[I + 1],
+                                     cell);
+          cspair.push_back(it != E.cells.begin() + E.ptr[I + 1] && *it == cell
+                               ? (int32_t)(it - E.cells.begin())
+                               : -1);
+          const int32_t *gl = &c->c2g[(size_t)cell * c->nloc];
+          for (int l = 0; l < c->nloc; ++l) clmap.push_back(c->boundary[gl[l]] ? -1 : pos[gl[l]]);
+        }
+        cptr[I + 1] = (int32_t)catom.size();
+        for (int32_t sI = E.snode_ptr[I]; sI < E.snode_ptr[I + 1]; ++sI) pos[E.snode[sI]] = -1;
+      }
+      c->ncpairs = (int64_t)catom.size();
+      std::vector<int32_t> eptr(c->n_cells + 1, 0), epair(ccell.size()), cpos(ccell.size());
+      for (int32_t cc : ccell) eptr[cc + 1]++;
+      for (int64_t cc = 0; cc < c->n_cells; ++cc) eptr[cc + 1] += eptr[cc];
+      std::vector<int32_t> fill(eptr.begin(), eptr.end() - 1);
+      for (size_t q = 0; q < ccell.size(); ++q) {
+        const int32_t at = fill[ccell[q]]++;
+        epair[at] = (int32_t)q;
+        cpos[q] = at;
+      }
+      std::vector<int64_t> noff(c->n_cells + 1, 0);
+      int maxr = 0;
+      for (int64_t cc = 0; cc < c->n_cells; ++cc) {
+        const int64_t ne = (int64_t)(eptr[cc + 1] - eptr[cc]) * c->nf;
+        const int64_t nep = (ne + 15) / 16 * 16;
+        noff[cc + 1] = noff[cc] + nep;
+        maxr = std::max<int>(maxr, (int)(nep / 16));
+      }
+      c->max_rbe = maxr;
+      c->n_epad = noff[c->n_cells];
+      if ((int64_t)maxr * 16 > EFE_MAX_CELL_ENR) {
+        c->err = "more than " + std::to_string(EFE_MAX_CELL_ENR) +
+                 " enrichment functions couple to one cell";
+        s = EFE_EINVAL;
+        goto fail;
+      }
+      TRY(upload(c, &c->d_cpair_atom, catom));
+      TRY(upload(c, &c->d_cpair_spair, cspair));
+      TRY(upload(c, &c->d_cpair_lmap, clmap));
+      TRY(upload(c, &c->d_cpair_ptr, cptr));
+      TRY(upload(c, &c->d_cell_eptr, eptr));
+      TRY(upload(c, &c->d_cell_epair, epair));
+      TRY(upload(c, &c->d_cpair_cpos, cpos));
+      TRY(upload(c, &c->d_cell_noff, noff));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
     std::vector<int32_t> items;
     build_items(c->natoms, c->n_nodes, E.snode_ptr, E.snode, 512, 1024, items, c->enr_items_off);
     c->n_enr_items = (int64_t)items.size() / 3;
@@ -404,6 +489,13 @@ fail:
 extern "C" efe_status efe_enrichment_amplification(const efe_ctx *c, double *amp) {
   if (!c || !amp) return EFE_EINVAL;
   *amp = c->amplification;
+  return EFE_OK;
+}
+
+extern "C" efe_status efe_get_coupling(const efe_ctx *c, int64_t *ncpairs, int64_t *max_cell) {
+  if (!c) return EFE_EINVAL;
+  if (ncpairs) *ncpairs = c->ncpairs;
+  if (max_cell) *max_cell = (int64_t)c->max_rbe * 16;
   return EFE_OK;
 }
 
@@ -463,7 +555,12 @@ extern "C" void efe_destroy(efe_ctx *c) {
                   c->d_kbnm_src,  c->d_Pc_nm,        c->d_kbtrip,     c->d_Pphi,
                   c->d_D,         c->d_vq,           c->d_Htile64,    c->d_Htile32,
                   c->d_Htile16,   c->d_enr_items,    c->d_kb_items,   c->d_g_ptr,
-                  c->d_g_atom,    c->d_nm_gslot,     c->d_Cg,         c->d_Bg};
+                  c->d_g_atom,    c->d_nm_gslot,     c->d_Cg,         c->d_Bg,
+                  c->d_cell_eptr, c->d_cell_epair,   c->d_cpair_cpos, c->d_cell_noff,
+                  c->d_Bkin_pair, c->d_B_pair,       c->d_Et64,       c->d_Ee64,
+                  c->d_Et32,      c->d_Ee32,         c->d_Hee,
+                  c->d_Ptil,      c->d_cpair_ptr,    c->d_cpair_atom, c->d_cpair_spair,
+                  c->d_cpair_lmap};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (auto &b : c->ws)

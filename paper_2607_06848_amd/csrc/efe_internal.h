@@ -15,6 +15,9 @@
 #define EFE_MAXP 6
 #define EFE_MAXQ 7
 #define EFE_MAXLOC ((EFE_MAXP + 1) * (EFE_MAXP + 1) * (EFE_MAXP + 1))
+// enrichment functions that may couple to one cell (padded to 16): 85 atoms
+// of 9 (the cell GEMM keeps their row numbers in LDS)
+#define EFE_MAX_CELL_ENR 768
 
 struct DevBuf {
   void *p = nullptr;
@@ -69,6 +72,28 @@ struct efe_ctx {
   int64_t n_gslots = 0;
   int32_t *d_g_ptr = nullptr, *d_g_atom = nullptr, *d_nm_gslot = nullptr;
   double *d_Cg = nullptr, *d_Bg = nullptr;
+  // coupling pairs (atom, cell): every cell holding one of the atom's support
+  // nodes (atom-major, by cell), with the support pair of the cell (-1 for
+  // the layer outside the support) and the local-to-support map; their
+  // cell-major view: per cell its pairs (ascending atom), per pair its
+  // cell-major position, per cell the prefix of its padded enrichment row
+  // count (functions x atoms rounded up to 16), which places its tiles
+  int64_t ncpairs = 0;
+  int32_t *d_cpair_atom = nullptr, *d_cpair_spair = nullptr, *d_cpair_lmap = nullptr;
+  int32_t *d_cpair_ptr = nullptr, *d_cpair_cpos = nullptr;
+  int32_t *d_cell_eptr = nullptr, *d_cell_epair = nullptr;
+  int64_t *d_cell_noff = nullptr;
+  int max_rbe = 0;                                     // max padded rows / 16 over cells
+  int64_t n_epad = 0;                                  // sum of padded rows
+  // per-pair cell blocks [pair][l][k]: kinetic part of B (setup), B (per potential)
+  double *d_Bkin_pair = nullptr, *d_B_pair = nullptr;
+  // coupling of the orthogonalized basis per cell, E_c = B_c - C_c H_c, in the
+  // MFMA operand layouts: Et = E_c^T tiles (rows: cell nodes, k: the cell's
+  // enrichment functions), Ee = E_c tiles (rows: enrichment functions, k: nodes)
+  double *d_Et64 = nullptr, *d_Ee64 = nullptr;
+  float *d_Et32 = nullptr, *d_Ee32 = nullptr;
+  double *d_Hee = nullptr;                             // H^E_ee without projectors
+  double *d_Ptil = nullptr;                            // P^phi - P^C C^T, [nproj][n_enr]
   // (cell, I, J) triples of atoms sharing a support cell
   int64_t ntrip = 0;
   int32_t *d_trip = nullptr;
@@ -174,17 +199,29 @@ efe_status efe_launch_local_potential(efe_ctx *ctx, double *vq);
 efe_status efe_gemm(efe_ctx *ctx, bool transA, bool transB, int64_t M, int64_t N, int64_t K,
                     double alpha, const double *A, int64_t lda, const double *B, int64_t ldb,
                     double beta, double *C, int64_t ldc, const double *wK = nullptr);
+// C += alpha op(A) B (op(A) = A or A^T), the sum over K split across blocks
+// and added atomically (row-major, as efe_gemm)
+efe_status efe_gemm_acc(efe_ctx *ctx, bool transA, int64_t M, int64_t N, int64_t K, double alpha,
+                        const double *A, int64_t lda, const double *B, int64_t ldb, double *C,
+                        int64_t ldc);
 // C += alpha A^T diag(w) B over K rows split across blocks (C must be summed into)
 efe_status efe_gram(efe_ctx *ctx, int64_t M, int64_t N, int64_t K, double alpha,
                     const double *A, int64_t lda, const double *B, int64_t ldb,
                     const double *w, double *C, int64_t ldc);
 
 // operator applications (apply.hip)
+// Affine epilogue of an H apply (the Chebyshev recurrence fused into the
+// assembly): Y = alpha H X + beta Z1 + gamma Z2 + alpha G diag(Cl), with Z1,
+// Z2, G in the layout of Y (Y may be Z2).  alpha = 1 and null terms: Y = H X.
+struct ApplyEpilogue {
+  double alpha = 1.0, beta = 0.0, gamma = 0.0;
+  const double *Z1 = nullptr, *Z2 = nullptr, *G = nullptr, *Cl = nullptr;
+};
 // Y = H^E X with X given as (XC scaled row-wise by `scale` if non-NULL, XE);
-// prec selects the cell GEMM / projector precision.
+// prec selects the cell GEMM precision; epi (may be NULL) the epilogue.
 efe_status efe_apply_H_internal(efe_ctx *ctx, const double *XC, int64_t ldx, const double *scale,
                                 const double *XE, int64_t lde, double *Y, int64_t ldy, int ncols,
-                                int prec);
+                                int prec, const ApplyEpilogue *epi = nullptr);
 efe_status efe_apply_M_internal(efe_ctx *ctx, const double *X, int64_t ldx, double *Y,
                                 int64_t ldy, int ncols);
 efe_status efe_apply_Minv_internal(efe_ctx *ctx, const double *X, int64_t ldx, double *Y,
@@ -199,8 +236,8 @@ efe_status efe_enr_block_inv(efe_ctx *ctx, const double *XE, int64_t ldx, double
 // ------------------------------------------------------------------ timing
 // Optional HIP-event timing of the hot-path kernels (efe_timing).
 #define EFE_T_CELL 0     // one colour pass of the cell GEMM
-#define EFE_T_PRE 1      // pre pass of an H apply
-#define EFE_T_POST 2     // enrichment rows of an H apply
+#define EFE_T_PRE 1      // projector pass and Y^C initialization of an H apply
+#define EFE_T_POST 2     // enrichment rows of an H apply (reduction and dense blocks)
 #define EFE_T_RECUR 3    // residual recurrence update
 #define EFE_T_APPLY 4    // a whole H apply
 #define EFE_T_RR 5       // a whole Rayleigh-Ritz

@@ -45,17 +45,6 @@ __global__ void k_residual_init(int64_t rows, int ncols, const double *__restric
   Zp[idx] = 0.0;
 }
 
-// Zn = a W + b Zc + gam Zp + a G Cl   (Zn may alias Zp)
-__global__ void k_recur(int64_t n, int ncols, double a, double b, double gam,
-                        const double *__restrict__ W, const double *__restrict__ Zc,
-                        const double *Zp, const double *__restrict__ G,
-                        const double *__restrict__ Cl, double *Zn) {
-  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (idx >= n * ncols) return;
-  const double zp = Zp[idx];
-  Zn[idx] = a * W[idx] + b * Zc[idx] + gam * zp + a * G[idx] * Cl[idx % ncols];
-}
-
 // V <- w_r Z + V Cl on CFE rows (w = 1/m), enrichment rows use ZE = M~ee^-1 Z^E
 __global__ void k_vout(int64_t n_nodes, int64_t rows, int ncols, const double *__restrict__ minv,
                        const double *__restrict__ Z, const double *__restrict__ ZE,
@@ -150,13 +139,22 @@ static efe_status filter_chunk(efe_ctx *c, double *V, const double *lambda, int3
   k_residual_init<<<nb, T, 0, c->stream>>>(rows, ncols, W, Zb, lambda, sig[1] / e, G, Zc, Zp);
   for (int k = 2; k <= m; ++k) {
     if ((s = efe_enr_block_inv(c, Zc + nn * ncols, ncols, XE, ncols, ncols))) return s;
-    // the recurrence's H applies run in the requested precision; G stays FP64
-    if ((s = efe_apply_H_internal(c, Zc, ncols, c->d_minv, XE, ncols, W, ncols, ncols, prm->prec)))
-      return s;
-    const double a = 2.0 * sig[k] / e;
+    // the recurrence's H applies run in the requested precision (G stays
+    // FP64); its three affine terms enter the assembly itself: Z_k is
+    // written in place of Z_{k-2}, starting from the terms and accumulating
+    // alpha H M~^-1 Z_{k-1} over the colour passes
+    ApplyEpilogue ep;
+    ep.alpha = 2.0 * sig[k] / e;
+    ep.beta = -cc * ep.alpha;
+    ep.gamma = -sig[k - 1] * sig[k];
+    ep.Z1 = Zc;
+    ep.Z2 = Zp;
+    ep.G = G;
+    ep.Cl = Cl + (int64_t)(k - 1) * ncols;
     const int t = efe_timer_begin(c, EFE_T_RECUR);
-    k_recur<<<nb, T, 0, c->stream>>>(rows, ncols, a, -cc * a, -sig[k - 1] * sig[k], W, Zc, Zp, G,
-                                     Cl + (int64_t)(k - 1) * ncols, Zp);
+    if ((s = efe_apply_H_internal(c, Zc, ncols, c->d_minv, XE, ncols, Zp, ncols, ncols, prm->prec,
+                                  &ep)))
+      return s;
     efe_timer_end(c, EFE_T_RECUR, t);
     std::swap(Zc, Zp);
   }

@@ -177,7 +177,8 @@ __global__ __launch_bounds__(256) void k_enr_pair_proj(
     const double *__restrict__ N3, const double *__restrict__ G3, const double *__restrict__ xyz,
     const double *__restrict__ nu, const int32_t *__restrict__ pair_atom,
     const int32_t *__restrict__ pair_cell, const int32_t *__restrict__ lmap,
-    const double *__restrict__ vq, double *__restrict__ out_b, double *__restrict__ out_k) {
+    const double *__restrict__ vq, double *__restrict__ out_b, double *__restrict__ out_k,
+    double *__restrict__ out_pair) {
   // weighted values at up to 64 quadrature points at a time
   __shared__ double sphi[9][64];
   __shared__ double sgrad[3][9][64];
@@ -225,6 +226,10 @@ __global__ __launch_bounds__(256) void k_enr_pair_proj(
   for (int r = 0; r < 2; ++r) {
     const int l = threadIdx.x + 256 * r;
     if (l >= nloc) continue;
+    // the cell's own block (kinetic part), kept per pair for the coupling
+    // E_c = B_c - C_c H_c of the orthogonalized basis
+    if (KIN && out_pair)
+      for (int k = 0; k < nf; ++k) out_pair[((int64_t)pr * nloc + l) * nf + k] = acck[r][k];
     const int32_t s = lmap[(int64_t)pr * nloc + l];
     if (s < 0) continue;
     for (int k = 0; k < nf; ++k) {
@@ -245,7 +250,8 @@ __global__ __launch_bounds__(256) void k_enr_pair_proj_v(
     const double *__restrict__ N3, const double *__restrict__ xyz, const double *__restrict__ nu,
     const int32_t *__restrict__ pair_atom, const int32_t *__restrict__ pair_cell,
     const int32_t *__restrict__ lmap, const double *__restrict__ vq, int KQ,
-    double *__restrict__ out_b) {
+    double *__restrict__ out_b, const double *__restrict__ kin_pair,
+    double *__restrict__ out_pair) {
   extern __shared__ double sphi[];   // [4 KQ][16]
   const int pr = blockIdx.x;
   const int I = pair_atom[pr], cell = pair_cell[pr];
@@ -283,6 +289,8 @@ __global__ __launch_bounds__(256) void k_enr_pair_proj_v(
     for (int v = 0; v < 4; ++v) {
       const int l = 16 * rb + 4 * v + lk;
       if (l < nloc && li < nf) {
+        const int64_t o = ((int64_t)pr * nloc + l) * nf + li;
+        if (out_pair) out_pair[o] = kin_pair[o] + acc[v];
         const int32_t sn = lmap[(int64_t)pr * nloc + l];
         if (sn >= 0) atomicAdd(&out_b[(int64_t)sn * nf + li], acc[v]);
       }
@@ -412,6 +420,192 @@ __global__ __launch_bounds__(256) void k_mee_rows(int nf, int64_t n_enr, const i
   __syncthreads();
   for (int64_t i = threadIdx.x; i < n_enr; i += blockDim.x)
     Mee[f * n_enr + i] = Mpp[f * n_enr + i] - acc[i];
+}
+
+// ------------------------------------------------------------ coupling
+// The orthogonalized basis couples the enrichment rows to the CFE rows
+// through H^ec = B - C H^cc (Sec. II.B: N^E = phi - C N^C).  Per cell,
+// E_c = B_c - C_c H_c (n_e x nloc: the cell's enrichment functions against
+// its nodes), formed here in FP64 so that the cancellation between B and
+// C H happens before any rounding to a reduced precision.  One work-group
+// takes a cell and 16 of its enrichment functions: C_c^T (nloc x 16) in LDS as
+// the B operand, the cell Hamiltonian's MFMA tiles as the A operand, each wave
+// a row block of H_c C_c^T.  The results go to both operand layouts of the
+// apply (E_c^T rows = nodes, E_c rows = functions; zero padding included).
+__global__ __launch_bounds__(256) void k_build_E(
+    int nloc, int RB, int KS, int nf, int max_cb, const double *__restrict__ Ht,
+    const int32_t *__restrict__ cell_eptr, const int32_t *__restrict__ cell_epair,
+    const int64_t *__restrict__ cell_noff, const int32_t *__restrict__ lmap,
+    const int32_t *__restrict__ spair, const double *__restrict__ C_am,
+    const double *__restrict__ B_pair,
+    double *__restrict__ Et, double *__restrict__ Ee, float *__restrict__ Et32,
+    float *__restrict__ Ee32) {
+  __shared__ double Cs[EFE_MAXLOC + 16][16];
+  const int64_t cell = blockIdx.x / max_cb;
+  const int cb = blockIdx.x % max_cb;
+  const int32_t p0 = cell_eptr[cell];
+  const int ne = (cell_eptr[cell + 1] - p0) * nf;
+  if (16 * cb >= ne) return;
+  const int nep = (ne + 15) / 16 * 16, kse_n = nep / 4;
+  const int64_t noff = cell_noff[cell];
+  for (int i = threadIdx.x; i < 4 * KS * 16; i += 256) {
+    const int l = i / 16, j = i % 16, e = 16 * cb + j;
+    double v = 0.0;
+    if (l < nloc && e < ne) {
+      const int32_t pr = cell_epair[p0 + e / nf];
+      const int32_t sn = lmap[(int64_t)pr * nloc + l];
+      if (sn >= 0) v = C_am[(int64_t)sn * nf + e % nf];
+    }
+    Cs[l][j] = v;
+  }
+  __syncthreads();
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, li = lane % 16, lk = lane / 16;
+  for (int rb = wave; rb < RB; rb += 4) {
+    const double *hp = Ht + ((int64_t)cell * RB + rb) * KS * 64 + lane;
+    v4d_p acc = {0.0, 0.0, 0.0, 0.0};
+    for (int ks = 0; ks < KS; ++ks)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(hp[(int64_t)ks * 64], Cs[4 * ks + lk][li], acc,
+                                                 0, 0, 0);
+    // accumulator v of lane l: node row 16 rb + 4 v + l/16, function 16 cb + l%16
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int l = 16 * rb + 4 * v + lk, e = 16 * cb + li;
+      double val = 0.0;
+      if (l < nloc && e < ne) {
+        const int32_t pr = cell_epair[p0 + e / nf], sp = spair[pr];
+        // B_c vanishes on the layer of cells outside the support
+        const double bv = sp >= 0 ? B_pair[((int64_t)sp * nloc + l) * nf + e % nf] : 0.0;
+        val = bv - acc[v];
+      }
+      // E_c^T tile: row l (block rb), k index e
+      const int64_t ot = 16 * (int64_t)RB * noff + ((int64_t)rb * kse_n + e / 4) * 64 +
+                         (l % 16) + 16 * (e % 4);
+      Et[ot] = val;
+      if (Et32) Et32[ot] = (float)val;
+      // E_c tile: row e (block e/16), k index l (k steps cover 4 KS nodes)
+      if (l < 4 * KS) {
+        const int64_t oe = 4 * (int64_t)KS * noff + ((int64_t)(e / 16) * KS + l / 4) * 64 +
+                           (e % 16) + 16 * (l % 4);
+        Ee[oe] = val;
+        if (Ee32) Ee32[oe] = (float)val;
+      }
+    }
+  }
+}
+
+// Rows of the enrichment block of the orthogonalized Hamiltonian without the
+// projectors, H^E_ee = H^phiphi - C B^T - E C^T (the expansion of T^T Hhat T
+// with E = B - C H^cc), first part: Hee = H^phiphi - C B^T, row f = (I, k)
+// summed over the support nodes of atom I and, at each node, the atoms whose
+// support holds it (B vanishes off the support).
+__global__ __launch_bounds__(256) void k_hee_rows(int nf, int64_t n_enr,
+                                                  const int32_t *__restrict__ snode_ptr,
+                                                  const int32_t *__restrict__ snode,
+                                                  const int32_t *__restrict__ nm_ptr,
+                                                  const int32_t *__restrict__ nm_atom,
+                                                  const int32_t *__restrict__ nm_src,
+                                                  const double *__restrict__ C_am,
+                                                  const double *__restrict__ B_am,
+                                                  const double *__restrict__ Hpp,
+                                                  double *__restrict__ Hee) {
+  extern __shared__ double acc[];
+  const int64_t f = blockIdx.x;
+  const int I = f / nf, k = f % nf;
+  for (int64_t i = threadIdx.x; i < n_enr; i += blockDim.x) acc[i] = 0.0;
+  __syncthreads();
+  for (int32_t s = snode_ptr[I] + threadIdx.x; s < snode_ptr[I + 1]; s += blockDim.x) {
+    const int32_t j = snode[s];
+    const double cf = C_am[(int64_t)s * nf + k];
+    for (int32_t ee = nm_ptr[j]; ee < nm_ptr[j + 1]; ++ee) {
+      const int J = nm_atom[ee];
+      const int64_t src = nm_src[ee];
+      for (int l = 0; l < nf; ++l) atomicAdd(&acc[J * nf + l], cf * B_am[src * nf + l]);
+    }
+  }
+  __syncthreads();
+  for (int64_t i = threadIdx.x; i < n_enr; i += blockDim.x)
+    Hee[f * n_enr + i] = Hpp[f * n_enr + i] - acc[i];
+}
+
+// Second part: Hee -= E C^T = sum over cells of E_c C_c^T (E is non-zero on
+// the cells that hold an atom's support nodes, one layer beyond its support,
+// so the product is taken cell by cell).  One work-group takes a cell and 16
+// of its enrichment functions e2: C_c^T (nodes x 16) in LDS as the B operand,
+// the E_c tiles as the A operand, each wave the row blocks e1 = wave + 4 i;
+// every 16 x 16 block is added into Hee atomically.
+__global__ __launch_bounds__(256) void k_hee_cells(
+    int nloc, int KS, int nf, int max_cb, int64_t n_enr, const int32_t *__restrict__ cell_eptr,
+    const int32_t *__restrict__ cell_epair, const int64_t *__restrict__ cell_noff,
+    const int32_t *__restrict__ cpair_atom, const int32_t *__restrict__ lmap,
+    const double *__restrict__ C_am, const double *__restrict__ Ee, double *__restrict__ Hee) {
+  __shared__ double Cs[EFE_MAXLOC + 16][16];
+  const int64_t cell = blockIdx.x / max_cb;
+  const int cb = blockIdx.x % max_cb;
+  const int32_t p0 = cell_eptr[cell];
+  const int ne = (cell_eptr[cell + 1] - p0) * nf;
+  if (16 * cb >= ne) return;
+  const int RBE = (ne + 15) / 16;
+  const int64_t noff = cell_noff[cell];
+  for (int i = threadIdx.x; i < 4 * KS * 16; i += 256) {
+    const int l = i / 16, j = i % 16, e = 16 * cb + j;
+    double v = 0.0;
+    if (l < nloc && e < ne) {
+      const int32_t pr = cell_epair[p0 + e / nf];
+      const int32_t sn = lmap[(int64_t)pr * nloc + l];
+      if (sn >= 0) v = C_am[(int64_t)sn * nf + e % nf];
+    }
+    Cs[l][j] = v;
+  }
+  __syncthreads();
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, li = lane % 16, lk = lane / 16;
+  const int e2 = 16 * cb + li;
+  const int64_t f2 = e2 < ne ? (int64_t)cpair_atom[cell_epair[p0 + e2 / nf]] * nf + e2 % nf : 0;
+  for (int b1 = wave; b1 < RBE; b1 += 4) {
+    const double *ap = Ee + 4 * (int64_t)KS * noff + (int64_t)b1 * KS * 64 + lane;
+    v4d_p acc = {0.0, 0.0, 0.0, 0.0};
+    for (int ks = 0; ks < KS; ++ks)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[(int64_t)ks * 64], Cs[4 * ks + lk][li], acc,
+                                                 0, 0, 0);
+    // accumulator v of lane l: function e1 = 16 b1 + 4 v + l/16, e2 = 16 cb + l%16
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int e1 = 16 * b1 + 4 * v + lk;
+      if (e1 < ne && e2 < ne) {
+        const int64_t f1 = (int64_t)cpair_atom[cell_epair[p0 + e1 / nf]] * nf + e1 % nf;
+        atomicAdd(&Hee[f1 * n_enr + f2], -acc[v]);
+      }
+    }
+  }
+}
+
+// Projector rows in the orthogonalized basis: P~^phi = P^phi - P^C C^T
+// (beta . (phi - C N^C)), one work-group per projector.
+__global__ __launch_bounds__(256) void k_ptilde(int nf, int64_t n_enr,
+                                                const int32_t *__restrict__ kbnode_ptr,
+                                                const int32_t *__restrict__ kbnode,
+                                                const double *__restrict__ Pc_am,
+                                                const int32_t *__restrict__ nm_ptr,
+                                                const int32_t *__restrict__ nm_atom,
+                                                const int32_t *__restrict__ nm_src,
+                                                const double *__restrict__ C_am,
+                                                const double *__restrict__ Pphi,
+                                                double *__restrict__ Pt) {
+  extern __shared__ double acc[];
+  const int K = blockIdx.x;
+  for (int64_t i = threadIdx.x; i < n_enr; i += blockDim.x) acc[i] = 0.0;
+  __syncthreads();
+  for (int32_t s = kbnode_ptr[K] + threadIdx.x; s < kbnode_ptr[K + 1]; s += blockDim.x) {
+    const int32_t j = kbnode[s];
+    const double pc = Pc_am[s];
+    for (int32_t ee = nm_ptr[j]; ee < nm_ptr[j + 1]; ++ee) {
+      const int J = nm_atom[ee];
+      const int64_t src = nm_src[ee];
+      for (int l = 0; l < nf; ++l) atomicAdd(&acc[J * nf + l], pc * C_am[src * nf + l]);
+    }
+  }
+  __syncthreads();
+  for (int64_t i = threadIdx.x; i < n_enr; i += blockDim.x)
+    Pt[(int64_t)K * n_enr + i] = Pphi[(int64_t)K * n_enr + i] - acc[i];
 }
 
 // Symmetrize a square matrix in place: A = (A + A^T)/2
@@ -753,9 +947,11 @@ efe_status efe_build_enrichment(efe_ctx *c) {
     k_enr_norm<<<c->npairs, 256, 0, c->stream>>>(g, e, c->d_xq1, c->d_W3, c->d_xyz,
                                                  c->d_pair_atom, c->d_pair_cell, c->d_nu);
     k_inv_sqrt<<<cdiv(ne, 256), 256, 0, c->stream>>>(ne, c->d_nu);
+    if ((s = efe_alloc(c, (void **)&c->d_Bkin_pair, (size_t)c->npairs * c->nloc * nf * 8)))
+      return s;
     k_enr_pair_proj<true><<<c->npairs, 256, 0, c->stream>>>(
         g, e, c->d_xq1, c->d_W3, c->d_N3, c->d_G3, c->d_xyz, c->d_nu, c->d_pair_atom,
-        c->d_pair_cell, c->d_pair_lmap, nullptr, c->d_b_am, c->d_Bkin_am);
+        c->d_pair_cell, c->d_pair_lmap, nullptr, c->d_b_am, c->d_Bkin_am, c->d_Bkin_pair);
     k_scale_by_minv<<<cdiv(ns, 256), 256, 0, c->stream>>>(c->n_snodes, nf, c->d_snode, c->d_minv,
                                                           c->d_b_am, c->d_C_am);
     k_to_group_major<<<cdiv(c->n_nodes, 256), 256, 0, c->stream>>>(
@@ -813,6 +1009,12 @@ efe_status efe_build_enrichment(efe_ctx *c) {
                                                    c->d_W3, c->d_xyz, c->d_nu, c->d_kbtrip, ne,
                                                    c->d_Pphi);
   }
+  // projector rows in the orthogonalized basis
+  if ((s = efe_alloc(c, (void **)&c->d_Ptil, (int64_t)np * ne * 8))) return s;
+  if (np > 0 && ne > 0)
+    k_ptilde<<<np, 256, ne * 8, c->stream>>>(nf, ne, c->d_kbnode_ptr, c->d_kbnode, c->d_Pc_am,
+                                             c->d_nm_ptr, c->d_nm_atom, c->d_nm_src, c->d_C_am,
+                                             c->d_Pphi, c->d_Ptil);
   HIPCHK(c, hipGetLastError());
   return EFE_OK;
 }
@@ -853,19 +1055,38 @@ efe_status efe_build_operators(efe_ctx *c, const double *vq, int precisions) {
   c->have16 = want16;
   if (nf > 0 && c->npairs > 0) {
     const int64_t ns = c->n_snodes * nf;
+    const size_t pb = (size_t)c->npairs * c->nloc * nf * 8;   // support pairs
+    if (!c->d_B_pair && (s = efe_alloc(c, (void **)&c->d_B_pair, pb))) return s;
+    if (!c->d_Hee && (s = efe_alloc(c, (void **)&c->d_Hee, ne * ne * 8))) return s;
+    const int64_t tT = 16 * (int64_t)c->RB * c->n_epad, tE = 4 * (int64_t)c->KS * c->n_epad;
+    if (!c->d_Et64 && (s = efe_alloc(c, (void **)&c->d_Et64, tT * 8))) return s;
+    if (!c->d_Ee64 && (s = efe_alloc(c, (void **)&c->d_Ee64, tE * 8))) return s;
+    if (want32 && !c->d_Et32 && (s = efe_alloc(c, (void **)&c->d_Et32, tT * 4))) return s;
+    if (want32 && !c->d_Ee32 && (s = efe_alloc(c, (void **)&c->d_Ee32, tE * 4))) return s;
     k_copy<<<cdiv(ns, 256), 256, 0, c->stream>>>(ns, c->d_Bkin_am, c->d_B_am);
     const int KQ = (int)cdiv(c->nqp, 4);
     k_enr_pair_proj_v<<<c->npairs, 256, (size_t)KQ * 64 * 8, c->stream>>>(
         g, e, c->d_xq1, c->d_W3, c->d_N3, c->d_xyz, c->d_nu, c->d_pair_atom, c->d_pair_cell,
-        c->d_pair_lmap, c->d_vq, KQ, c->d_B_am);
-    k_to_group_major<<<cdiv(c->n_nodes, 256), 256, 0, c->stream>>>(
-        c->n_nodes, nf, c->d_nm_ptr, c->d_nm_src, c->d_nm_gslot, c->d_B_am, c->d_Bg);
+        c->d_pair_lmap, c->d_vq, KQ, c->d_B_am, c->d_Bkin_pair, c->d_B_pair);
     k_copy<<<cdiv(ne * ne, 256), 256, 0, c->stream>>>(ne * ne, c->d_Hpp_kin, c->d_Hpp);
     if (c->ntrip > 0)
       k_enr_pp<false><<<c->ntrip, 128, 0, c->stream>>>(g, e, c->d_xq1, c->d_W3, c->d_xyz,
                                                        c->d_nu, c->d_trip, c->d_vq, ne, nullptr,
                                                        c->d_Hpp);
     k_symmetrize<<<cdiv(ne * ne, 256), 256, 0, c->stream>>>(ne, c->d_Hpp);
+    // coupling of the orthogonalized basis: E_c per cell, then
+    // H^E_ee = H^phiphi - C B^T - sum_c E_c C_c^T
+    k_build_E<<<c->n_cells * c->max_rbe, 256, 0, c->stream>>>(
+        c->nloc, c->RB, c->KS, nf, c->max_rbe, c->d_Htile64, c->d_cell_eptr, c->d_cell_epair,
+        c->d_cell_noff, c->d_cpair_lmap, c->d_cpair_spair, c->d_C_am, c->d_B_pair, c->d_Et64,
+        c->d_Ee64, want32 ? c->d_Et32 : nullptr, want32 ? c->d_Ee32 : nullptr);
+    k_hee_rows<<<ne, 256, ne * 8, c->stream>>>(nf, ne, c->d_snode_ptr, c->d_snode, c->d_nm_ptr,
+                                               c->d_nm_atom, c->d_nm_src, c->d_C_am, c->d_B_am,
+                                               c->d_Hpp, c->d_Hee);
+    k_hee_cells<<<c->n_cells * c->max_rbe, 256, 0, c->stream>>>(
+        c->nloc, c->KS, nf, c->max_rbe, ne, c->d_cell_eptr, c->d_cell_epair, c->d_cell_noff,
+        c->d_cpair_atom, c->d_cpair_lmap, c->d_C_am, c->d_Ee64, c->d_Hee);
+    k_symmetrize<<<cdiv(ne * ne, 256), 256, 0, c->stream>>>(ne, c->d_Hee);
   }
   HIPCHK(c, hipGetLastError());
   c->have_potential = true;

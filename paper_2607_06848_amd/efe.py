@@ -85,6 +85,7 @@ _SIGS = {
                                         ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
     "efe_get_sizes": (ctypes.c_int32, [ctypes.c_void_p, c_int64_p]),
     "efe_enrichment_amplification": (ctypes.c_int32, [ctypes.c_void_p, c_double_p]),
+    "efe_get_coupling": (ctypes.c_int32, [ctypes.c_void_p, c_int64_p, c_int64_p]),
     "efe_get_tables": (ctypes.c_int32, [ctypes.c_void_p, c_int32_p, c_int32_p, c_int32_p,
                                         c_uint8_p]),
     "efe_get_support": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, c_int64_p, c_int32_p,
@@ -202,6 +203,13 @@ class Context:
         self._check(L.efe_get_sizes(self.h, sz))
         (self.rows, self.n_nodes, self.n_dof, self.n_enr, self.n_cells, self.n_qpts,
          self.natoms, self.nloc) = [int(v) for v in sz]
+
+    def coupling(self):
+        """(number of (atom, cell) coupling pairs, largest number of enrichment
+        functions coupled to one cell)"""
+        n, m = ctypes.c_int64(), ctypes.c_int64()
+        self._check(lib().efe_get_coupling(self.h, ctypes.byref(n), ctypes.byref(m)))
+        return n.value, m.value
 
     def amplification(self):
         a = ctypes.c_double()
