@@ -188,6 +188,22 @@ efe_status efe_enrichment_amplification(const efe_ctx *ctx, double *amp);
 efe_status efe_cheb_filter(efe_ctx *ctx, double *V, const double *lambda, int32_t ncols,
                            int64_t ld, const efe_cheb_params *prm);
 
+/* For callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * filter as efe_cheb_filter with every workspace taken from a fixed region of
+ * EFE_NOALLOC_SCRATCH_BYTES of device memory that the library holds on each
+ * GPU it runs on until the process ends (its address on a device is taken
+ * when the first context on that device is set up).  No device memory is
+ * allocated or freed.  EFE_EINVAL when the call's workspaces (about
+ * 4 x rows x min(ncols, 160) doubles plus the apply's) exceed the region;
+ * EFE_ESTATE if the region is unavailable on the context's device.  Every call
+ * on a GPU shares that GPU's region and leaves its contents behind: calls that
+ * overlap on one GPU (other streams, other host threads) race and must not
+ * be issued. */
+#define EFE_NOALLOC_SCRATCH_BYTES (64u << 20)
+efe_status efe_cheb_filter_noalloc(efe_ctx *ctx, double *V, const double *lambda, int32_t ncols,
+                                   int64_t ld, const efe_cheb_params *prm);
+
 /* Rayleigh-Ritz in FP64 (Eq. projectedKSEig): S = V^T M V, Hp = V^T H V,
  * Hp R = S R Lambda with R^T S R = I (dense generalized eigensolve on the
  * GPU: Cholesky of S, reduction, divide and conquer), V <- V R.

@@ -23,6 +23,22 @@ efe_status efe_alloc(efe_ctx *ctx, void **p, size_t bytes) {
 }
 
 efe_status efe_ws(efe_ctx *ctx, int slot, size_t bytes, void **p) {
+  if (ctx->arena) {
+    // no allocation: the slot gets (or has) a fixed place in the arena
+    if (slot < 0 || slot >= efe_ctx::kArenaSlots) EFE_FAIL(ctx, EFE_EINVAL, "bad scratch slot");
+    if (ctx->arena_len[slot] == 0) {
+      const size_t off = (ctx->arena_used + 255) & ~(size_t)255;
+      if (off + bytes > ctx->arena_cap)
+        EFE_FAIL(ctx, EFE_EINVAL, "the scratch region is too small for this call");
+      ctx->arena_off[slot] = off;
+      ctx->arena_len[slot] = std::max<size_t>(bytes, 1);
+      ctx->arena_used = off + ctx->arena_len[slot];
+    } else if (ctx->arena_len[slot] < bytes) {
+      EFE_FAIL(ctx, EFE_EINVAL, "a scratch slot grew within one call");
+    }
+    *p = ctx->arena + ctx->arena_off[slot];
+    return EFE_OK;
+  }
   if ((int)ctx->ws.size() <= slot) ctx->ws.resize(slot + 1);
   DevBuf &b = ctx->ws[slot];
   if (b.bytes < bytes) {
@@ -476,6 +492,7 @@ extern "C" efe_status efe_setup_mesh(const efe_mesh_desc *mesh, const efe_system
     HIPCHK(c, hipStreamSynchronize(c->stream));   // host vectors go out of scope
     TRY(efe_build_enrichment(c));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    TRY(efe_scratch_attach(c));
   }
 #undef TRY
   *out = c;

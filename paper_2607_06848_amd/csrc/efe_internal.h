@@ -130,6 +130,13 @@ struct efe_ctx {
 
   // workspaces (grown on demand)
   std::vector<DevBuf> ws;
+  // while an entry point that allocates nothing runs, workspace slots are
+  // carved out of the caller-fixed region [arena, arena + arena_cap) instead
+  // (slot -> offset, bytes; reset for every call)
+  char *arena = nullptr;
+  size_t arena_cap = 0, arena_used = 0;
+  static constexpr int kArenaSlots = 64;
+  size_t arena_off[kArenaSlots] = {0}, arena_len[kArenaSlots] = {0};
 
   // SCF state (scf.hip)
   void *scf = nullptr;
@@ -159,6 +166,9 @@ struct efe_ctx {
   } while (0)
 
 efe_status efe_alloc(efe_ctx *ctx, void **p, size_t bytes);
+// per-device address of the static scratch region of efe_cheb_filter_noalloc
+// (noalloc.hip), taken once per device at context setup
+efe_status efe_scratch_attach(efe_ctx *ctx);
 // rocBLAS handle bound to the context's stream (rr.hip)
 efe_status efe_blas_handle(efe_ctx *ctx, void **handle);
 void efe_blas_destroy(efe_ctx *ctx);
@@ -230,6 +240,11 @@ efe_status efe_apply_Minv_internal(efe_ctx *ctx, const double *X, int64_t ldx, d
 efe_status efe_transform_cfe(efe_ctx *ctx, const double *X, int64_t ldx, double *Xh, int64_t ldh,
                              int ncols);
 void efe_scf_free(efe_ctx *ctx);
+// argument checks and the column-chunk loop of efe_cheb_filter (filter.hip)
+efe_status efe_filter_check(efe_ctx *ctx, double *V, const double *lambda, int32_t ncols,
+                            int64_t ld, const efe_cheb_params *prm);
+efe_status efe_filter_run(efe_ctx *ctx, double *V, const double *lambda, int32_t ncols,
+                          int64_t ld, const efe_cheb_params *prm);
 efe_status efe_enr_block_inv(efe_ctx *ctx, const double *XE, int64_t ldx, double *YE,
                              int64_t ldy, int ncols);
 

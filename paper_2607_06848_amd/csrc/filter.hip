@@ -14,6 +14,15 @@
 
 #include "efe_device.h"
 
+// sigma_1 = e / (a_min - c), sigma_k = 1 / (2 / sigma_1 - sigma_{k-1})
+__global__ void k_sigma_table(int m, double a, double b, double a_min, double *__restrict__ sig) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double cc = 0.5 * (a + b), e = 0.5 * (b - a);
+  sig[0] = 0.0;
+  sig[1] = e / (a_min - cc);
+  for (int k = 2; k <= m; ++k) sig[k] = 1.0 / (2.0 / sig[1] - sig[k - 1]);
+}
+
 // C_k(lambda_j), k = 0..m, by the scalar recurrence (one thread per column)
 __global__ void k_cheb_table(int m, int ncols, const double *__restrict__ lam, double c, double e,
                              const double *__restrict__ sig, double *__restrict__ T) {
@@ -103,7 +112,9 @@ static efe_status filter_chunk(efe_ctx *c, double *V, const double *lambda, int3
   if ((s = efe_ws(c, 6, (size_t)std::max<int64_t>(c->n_enr, 1) * ncols * 8, (void **)&XE))) return s;
   if ((s = efe_ws(c, 7, (size_t)(m + 1) * ncols * 8, (void **)&Cl))) return s;
   if ((s = efe_ws(c, 8, (size_t)(m + 1) * 8, (void **)&dsig))) return s;
-  HIPCHK(c, hipMemcpyAsync(dsig, sig.data(), (m + 1) * 8, hipMemcpyHostToDevice, c->stream));
+  // the same table on the device (the same IEEE operations in the same order
+  // as the host's, so both hold identical values)
+  k_sigma_table<<<1, 1, 0, c->stream>>>(m, prm->a, prm->b, prm->a_min, dsig);
   const int T = 256;
   const int64_t nb = cdiv(blk, T);
 
@@ -164,8 +175,8 @@ static efe_status filter_chunk(efe_ctx *c, double *V, const double *lambda, int3
   return EFE_OK;
 }
 
-extern "C" efe_status efe_cheb_filter(efe_ctx *c, double *V, const double *lambda, int32_t ncols,
-                                      int64_t ld, const efe_cheb_params *prm) {
+efe_status efe_filter_check(efe_ctx *c, double *V, const double *lambda, int32_t ncols,
+                            int64_t ld, const efe_cheb_params *prm) {
   if (!c) return EFE_EINVAL;
   if (!V || !prm || ncols < 0 || ld < ncols || ld < 1) EFE_FAIL(c, EFE_EINVAL, "bad arguments");
   if (prm->degree < 1) EFE_FAIL(c, EFE_EINVAL, "degree must be >= 1");
@@ -180,12 +191,24 @@ extern "C" efe_status efe_cheb_filter(efe_ctx *c, double *V, const double *lambd
              "BF16 filter refused: enrichment amplification " + std::to_string(c->amplification) +
                  " exceeds " + std::to_string(EFE_BF16_MAX_AMPLIFICATION));
   if (!c->have_potential) EFE_FAIL(c, EFE_ESTATE, "no potential set");
+  return EFE_OK;
+}
+
+efe_status efe_filter_run(efe_ctx *c, double *V, const double *lambda, int32_t ncols, int64_t ld,
+                          const efe_cheb_params *prm) {
   efe_status s;
   for (int32_t j0 = 0; j0 < ncols; j0 += EFE_COL_CHUNK) {
     const int32_t nc = std::min<int32_t>(EFE_COL_CHUNK, ncols - j0);
     if ((s = filter_chunk(c, V + j0, lambda ? lambda + j0 : nullptr, nc, ld, prm))) return s;
   }
   return EFE_OK;
+}
+
+extern "C" efe_status efe_cheb_filter(efe_ctx *c, double *V, const double *lambda, int32_t ncols,
+                                      int64_t ld, const efe_cheb_params *prm) {
+  efe_status s = efe_filter_check(c, V, lambda, ncols, ld, prm);
+  if (s) return s;
+  return efe_filter_run(c, V, lambda, ncols, ld, prm);
 }
 
 // ------------------------------------------------------------------ Lanczos

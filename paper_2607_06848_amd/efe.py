@@ -105,6 +105,9 @@ _SIGS = {
     "efe_cheb_filter": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.c_int32, ctypes.c_int64,
                                          ctypes.POINTER(ChebParams)]),
+    "efe_cheb_filter_noalloc": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p,
+                                                 ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                                                 ctypes.POINTER(ChebParams)]),
     "efe_rayleigh_ritz": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                            ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]),
     "efe_set_density": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p]),
@@ -326,6 +329,14 @@ class Context:
         p = ChebParams(int(degree), float(a), float(b), float(a_min), int(mode), int(prec))
         lp = _ptr(lam) if lam is not None else None
         self._check(lib().efe_cheb_filter(self.h, _ptr(V), lp, n, ld, ctypes.byref(p)))
+        return V
+
+    def cheb_filter_noalloc(self, V, lam, degree, a, b, a_min, mode=EFE_FILTER_RESIDUAL,
+                            prec=EFE_FP64):
+        n, ld = self._block(V)
+        p = ChebParams(int(degree), float(a), float(b), float(a_min), int(mode), int(prec))
+        lp = _ptr(lam) if lam is not None else None
+        self._check(lib().efe_cheb_filter_noalloc(self.h, _ptr(V), lp, n, ld, ctypes.byref(p)))
         return V
 
     def rayleigh_ritz(self, V, want_res=True):
