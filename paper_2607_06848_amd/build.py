@@ -30,8 +30,7 @@ def build(verbose=False, jobs=8):
             procs = []
     _wait(procs, verbose)
     tmp = LIB + ".tmp"
-    cmd = (["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs +
-           ["-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"])
+    cmd = (["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs)
     out = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     if out.returncode != 0:
         raise RuntimeError("link of libefe.so failed:\n" + out.stdout)

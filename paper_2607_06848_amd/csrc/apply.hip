@@ -594,52 +594,70 @@ __device__ inline double epi_terms(const EpiArgs &e, int64_t o, int col) {
 
 // Y^C[node] = alpha sum_e P^C_e W[atom_e] + epilogue terms on every interior
 // node (boundary rows 0): the projector expansion, and the start value of the
-// colour passes' read-modify-write.  One wave per 8 consecutive nodes, three
-// columns per lane.  The nodes' entry pointers and (when the group has at most
-// 64 entries, as usual) their entries come in by vector loads and reach the
-// wave by readlane.
+// colour passes' read-modify-write.  Flat over (node, column pair): a thread
+// takes two adjacent columns of one node, so every array is read and written
+// in coalesced 16-byte pieces, and the threads of a wave share one or two
+// nodes, whose projector entries they loop over together.  Even ld (the host
+// checks it) keeps the pairs aligned.
 __global__ __launch_bounds__(256) void k_expand_init(int64_t n_nodes, int ncols,
                                                      const int32_t *__restrict__ kbnm_ptr,
                                                      const int32_t *__restrict__ kbnm_atom,
                                                      const double *__restrict__ Pc_nm,
                                                      const double *__restrict__ W,
                                                      const double *__restrict__ minv,
-                                                     EpiArgs e, double *Y, int64_t ldy) {
-  const int64_t grp =
-      (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
-  const int64_t n0 = grp * 8;
-  if (n0 >= n_nodes) return;
-  const int lane = threadIdx.x % 64;
-  const int nn = (int)min<int64_t>(8, n_nodes - n0);
-  const int32_t pv = kbnm_ptr ? kbnm_ptr[n0 + min(lane, nn)] : 0;
-  const int32_t eb = __builtin_amdgcn_readlane(pv, 0), ee = __builtin_amdgcn_readlane(pv, nn);
-  const bool vec = ee - eb <= 64;
-  const int32_t el = min(eb + lane, max(ee - 1, eb));
-  const int32_t av = ee > eb ? kbnm_atom[el] : 0;
-  const double cv = ee > eb ? Pc_nm[el] : 0.0;
-  for (int c0 = 0; c0 < ncols; c0 += 64 * POST_Q) {
-    for (int j = 0; j < nn; ++j) {
-      const int32_t e0 = __builtin_amdgcn_readlane(pv, j);
-      const int32_t e1 = __builtin_amdgcn_readlane(pv, j + 1);
-      double acc[POST_Q] = {0.0, 0.0, 0.0};
-      for (int32_t en = e0; en < e1; ++en) {
-        const int32_t atom = vec ? __builtin_amdgcn_readlane(av, en - eb) : kbnm_atom[en];
-        const double p = vec ? lane_bcast(cv, en - eb) : Pc_nm[en];
-        const double *w = W + (int64_t)atom * ncols;
-#pragma unroll
-        for (int q = 0; q < POST_Q; ++q) acc[q] += p * w[min(c0 + 64 * q + lane, ncols - 1)];
-      }
-      const int64_t node = n0 + j;
-      const bool inner = minv[node] != 0.0;
-#pragma unroll
-      for (int q = 0; q < POST_Q; ++q) {
-        const int col = c0 + 64 * q + lane;
-        if (col >= ncols) continue;
-        const int64_t o = node * ldy + col;
-        const double v = e.alpha * acc[q] + epi_terms(e, o, col);
-        Y[o] = inner ? v : 0.0;
-      }
+                                                     EpiArgs e, double *Y, int64_t ldy,
+                                                     bool vec) {
+  const int npr = (ncols + 1) / 2;
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= n_nodes * npr) return;
+  const int64_t node = idx / npr;
+  const int c0 = 2 * (int)(idx % npr);
+  const bool two = c0 + 1 < ncols;
+  double a0 = 0.0, a1 = 0.0;
+  if (kbnm_ptr) {
+    const int32_t e0 = kbnm_ptr[node], e1 = kbnm_ptr[node + 1];
+    for (int32_t en = e0; en < e1; ++en) {
+      const double p = Pc_nm[en];
+      const double *w = W + (int64_t)kbnm_atom[en] * ncols + c0;
+      a0 += p * w[0];
+      if (two) a1 += p * w[1];
     }
+  }
+  const int64_t o = node * ldy + c0;
+  const bool inner = minv[node] != 0.0;
+  // pairs by 16-byte accesses when the layout allows it (vec: even ld,
+  // aligned arrays), else element by element
+  auto ld2 = [&](const double *p) -> double2 {
+    if (vec && two) return *reinterpret_cast<const double2 *>(p + o);
+    double2 r;
+    r.x = p[o];
+    r.y = two ? p[o + 1] : 0.0;
+    return r;
+  };
+  double2 v;
+  v.x = e.alpha * a0;
+  v.y = e.alpha * a1;
+  if (e.Z1) {
+    const double2 z = ld2(e.Z1);
+    v.x += e.beta * z.x;
+    v.y += e.beta * z.y;
+  }
+  if (e.Z2) {
+    const double2 z = ld2(e.Z2);
+    v.x += e.gamma * z.x;
+    v.y += e.gamma * z.y;
+  }
+  if (e.G) {
+    const double2 g = ld2(e.G);
+    v.x += e.alpha * g.x * e.Cl[c0];
+    v.y += e.alpha * g.y * (two ? e.Cl[c0 + 1] : 0.0);
+  }
+  if (!inner) v.x = v.y = 0.0;
+  if (vec && two) {
+    *reinterpret_cast<double2 *>(Y + o) = v;
+  } else {
+    Y[o] = v.x;
+    if (two) Y[o + 1] = v.y;
   }
 }
 
@@ -826,9 +844,11 @@ efe_status efe_apply_H_internal(efe_ctx *c, const double *XC, int64_t ldx, const
               ncols, c->d_kb_items, xs, c->d_kbnode, c->d_Pc_am, XC, ldx, scale, c->d_D, W);
       }
     }
-    k_expand_init<<<cdiv(nn, 32), 256, 0, c->stream>>>(
+    auto al = [](const double *p) { return p == nullptr || (uintptr_t)p % 16 == 0; };
+    const bool vec = ldy % 2 == 0 && al(Y) && al(ep.Z1) && al(ep.Z2) && al(ep.G);
+    k_expand_init<<<cdiv(nn * ((ncols + 1) / 2), 256), 256, 0, c->stream>>>(
         nn, ncols, c->nproj ? c->d_kbnm_ptr : nullptr, c->d_kbnm_atom, c->d_Pc_nm, W, c->d_minv,
-        ec, Y, ldy);
+        ec, Y, ldy, vec);
     efe_timer_end(c, EFE_T_PRE, t);
   }
   // 2. cell GEMM, colour by colour: 160-column register tiles; a single
@@ -867,10 +887,12 @@ efe_status efe_apply_H_internal(efe_ctx *c, const double *XC, int64_t ldx, const
   const int t_post = efe_timer_begin(c, EFE_T_POST);
   if (ne) {
     k_fill_zero<<<cdiv(ne * ncols, 256), 256, 0, c->stream>>>(ne * ncols, TE);
-    if ((s = efe_gemm_acc(c, false, ne, ncols, ne, 1.0, c->d_Hee, ne, XE, lde, TE, ncols)))
+    if ((s = efe_dgemm(c, false, false, ne, ncols, ne, 1.0, c->d_Hee, ne, XE, lde, 1.0, TE, ncols,
+                               nullptr, true)))
       return s;
     if (c->nproj &&
-        (s = efe_gemm_acc(c, true, ne, ncols, c->nproj, 1.0, c->d_Ptil, ne, W, ncols, TE, ncols)))
+        (s = efe_dgemm(c, true, false, ne, ncols, c->nproj, 1.0, c->d_Ptil, ne, W, ncols, 1.0, TE,
+                            ncols, nullptr, true)))
       return s;
     EpiArgs ee = ec;
     if (ee.Z1) ee.Z1 += nn * ldy;
@@ -903,7 +925,7 @@ efe_status efe_apply_M_internal(efe_ctx *c, const double *X, int64_t ldx, double
                                                                    X, ldx, Y, ldy);
   HIPCHK(c, hipGetLastError());
   if (c->n_enr)
-    return efe_gemm(c, false, false, c->n_enr, ncols, c->n_enr, 1.0, c->d_Mee, c->n_enr,
+    return efe_dgemm(c, false, false, c->n_enr, ncols, c->n_enr, 1.0, c->d_Mee, c->n_enr,
                     X + c->n_nodes * ldx, ldx, 0.0, Y + c->n_nodes * ldy, ldy);
   return EFE_OK;
 }

@@ -558,7 +558,6 @@ extern "C" void efe_destroy(efe_ctx *c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
   efe_scf_free(c);
-  efe_blas_destroy(c);
   void *ptrs[] = {c->d_c2g,       c->d_colour_order, c->d_m,          c->d_minv, c->d_m_int,
                   c->d_N3,        c->d_G3,           c->d_W3,         c->d_K,
                   c->d_xq1,       c->d_xyz,          c->d_Zs,         c->d_pair_atom,

@@ -141,7 +141,7 @@ struct efe_ctx {
   // SCF state (scf.hip)
   void *scf = nullptr;
   // rocBLAS handle of the dense eigensolver (created on first use)
-  void *blas = nullptr;
+  int rr_sweeps = 0;          // block Jacobi sweeps of the last Rayleigh-Ritz
 
   // event timing (efe_timing)
   bool timing = false;
@@ -170,8 +170,6 @@ efe_status efe_alloc(efe_ctx *ctx, void **p, size_t bytes);
 // (noalloc.hip), taken once per device at context setup
 efe_status efe_scratch_attach(efe_ctx *ctx);
 // rocBLAS handle bound to the context's stream (rr.hip)
-efe_status efe_blas_handle(efe_ctx *ctx, void **handle);
-void efe_blas_destroy(efe_ctx *ctx);
 // message returned by efe_last_error(NULL) (calls that take no context)
 void efe_set_global_error(const std::string &msg);
 // workspace slot `slot` of at least `bytes` bytes (kept across calls)
@@ -203,21 +201,37 @@ efe_status efe_build_enrichment(efe_ctx *ctx);
 efe_status efe_build_operators(efe_ctx *ctx, const double *vq, int precisions);
 efe_status efe_launch_local_potential(efe_ctx *ctx, double *vq);
 
-// linear algebra helpers (blas.hip)
-// C[M x N] = alpha * op(A) op(B) (+ beta C); row-major; op(A) = A[M x K] or A^T
-// (A stored K x M); wK (may be NULL) weights the sum over k.
-efe_status efe_gemm(efe_ctx *ctx, bool transA, bool transB, int64_t M, int64_t N, int64_t K,
-                    double alpha, const double *A, int64_t lda, const double *B, int64_t ldb,
-                    double beta, double *C, int64_t ldc, const double *wK = nullptr);
-// C += alpha op(A) B (op(A) = A or A^T), the sum over K split across blocks
-// and added atomically (row-major, as efe_gemm)
-efe_status efe_gemm_acc(efe_ctx *ctx, bool transA, int64_t M, int64_t N, int64_t K, double alpha,
-                        const double *A, int64_t lda, const double *B, int64_t ldb, double *C,
-                        int64_t ldc);
-// C += alpha A^T diag(w) B over K rows split across blocks (C must be summed into)
-efe_status efe_gram(efe_ctx *ctx, int64_t M, int64_t N, int64_t K, double alpha,
-                    const double *A, int64_t lda, const double *B, int64_t ldb,
-                    const double *w, double *C, int64_t ldc);
+// dense FP64 linear algebra on the matrix cores (dense.hip)
+// C[M x N] = alpha op(A) op(B) + beta C, row-major; op(A) = A (M x K, lda)
+// or A^T (A stored K x M); op(B) = B (K x N) or B^T (B stored N x K); wK
+// (may be NULL) weights the sum over k.  split: the sum over K is spread over
+// work-groups whose partial products are added to C atomically, C += alpha
+// op(A) op(B) (beta ignored; for tall-skinny Grams and short outputs).
+efe_status efe_dgemm(efe_ctx *ctx, bool transA, bool transB, int64_t M, int64_t N, int64_t K,
+                     double alpha, const double *A, int64_t lda, const double *B, int64_t ldb,
+                     double beta, double *C, int64_t ldc, const double *wK = nullptr,
+                     bool split = false);
+// C += A^T diag(wK) B (N x N from K rows; A, B stored K x N) on the tiles on
+// and above the diagonal only; efe_mirror_upper then copies the upper
+// triangle into the lower
+efe_status efe_gram_sym(efe_ctx *ctx, int64_t N, int64_t K, const double *A, int64_t lda,
+                        const double *B, int64_t ldb, double *C, int64_t ldc,
+                        const double *wK = nullptr);
+efe_status efe_mirror_upper(efe_ctx *ctx, int64_t n, double *C, int64_t ldc);
+// A = L L^T in place (lower triangle of the symmetric positive definite n x n
+// A; the upper triangle outside the diagonal blocks is left undefined);
+// *dflag (device) is set to 1 when a pivot is not positive
+efe_status efe_potrf(efe_ctx *ctx, int64_t n, double *A, int64_t lda, int *dflag);
+// X = L^-1 for the lower triangular L (n x n; X full, zero above the diagonal)
+efe_status efe_trtri_lower(efe_ctx *ctx, int64_t n, const double *L, int64_t ldl, double *X,
+                           int64_t ldx);
+// H = Q diag(w) Q^T for the symmetric n x n H (both triangles read and
+// averaged): w ascending (device, n), Q row-major n x n with the eigenvectors
+// as columns.  work: efe_syev_work(n) doubles; iwork: efe_syev_iwork(n) ints.
+efe_status efe_syev_jacobi(efe_ctx *ctx, int64_t n, const double *H, int64_t ldh, double *w,
+                           double *Q, double *work, int *iwork, int *sweeps);
+size_t efe_syev_work(int64_t n);
+size_t efe_syev_iwork(int64_t n);
 
 // operator applications (apply.hip)
 // Affine epilogue of an H apply (the Chebyshev recurrence fused into the

@@ -4,14 +4,12 @@
 //   W  = H V                      (column chunks of the cell GEMM's width)
 //   S  = V^T M V  (lumped mass on CFE rows, M^ee on enrichment rows)
 //   Hp = V^T W
-//   Hp R = S R Lambda, R^T S R = I (dense generalized eigensolve, rocSOLVER
-//   sygvd: Cholesky of S, reduction, divide and conquer), ascending Lambda
+//   S = L L^T, A = L^-1 Hp L^-T, A = Q Lambda Q^T (block Jacobi), R = L^-T Q:
+//   Hp R = S R Lambda, R^T S R = I, ascending Lambda
 //   V <- V R, W <- W R (row blocks, in place),
 //   resnorm_j = ||W e_j - lambda_j M V e_j||
+// Every product runs on the FP64 matrix cores (dense.hip).
 #include <cmath>
-
-#include <rocblas/rocblas.h>
-#include <rocsolver/rocsolver.h>
 
 #include "efe_device.h"
 
@@ -54,24 +52,6 @@ __global__ void k_copy_masked(int64_t r0, int64_t n_nodes, int64_t nr, int N,
   V[r * ld + j] = (g < n_nodes && minv[g] == 0.0) ? 0.0 : T[idx];
 }
 
-efe_status efe_blas_handle(efe_ctx *c, void **h) {
-  if (!c->blas) {
-    rocblas_handle hb;
-    if (rocblas_create_handle(&hb) != rocblas_status_success)
-      EFE_FAIL(c, EFE_EHIP, "rocblas_create_handle failed");
-    c->blas = hb;
-  }
-  if (rocblas_set_stream((rocblas_handle)c->blas, c->stream) != rocblas_status_success)
-    EFE_FAIL(c, EFE_EHIP, "rocblas_set_stream failed");
-  *h = c->blas;
-  return EFE_OK;
-}
-
-void efe_blas_destroy(efe_ctx *c) {
-  if (c->blas) (void)rocblas_destroy_handle((rocblas_handle)c->blas);
-  c->blas = nullptr;
-}
-
 // rows of the in-place rotation per pass
 static int64_t rot_rows(int32_t N) { return std::max<int64_t>(64, (int64_t)(256 << 20) / (8 * N)); }
 
@@ -81,20 +61,23 @@ extern "C" efe_status efe_rayleigh_ritz(efe_ctx *c, double *V, int32_t N, int64_
   if (!V || !lambda || N < 1 || ld < N) EFE_FAIL(c, EFE_EINVAL, "bad arguments");
   if (!c->have_potential) EFE_FAIL(c, EFE_ESTATE, "no potential set");
   efe_status s;
-  void *hv;
-  if ((s = efe_blas_handle(c, &hv))) return s;
-  rocblas_handle h = (rocblas_handle)hv;
   const int64_t rows = c->rows, nn = c->n_nodes, ne = c->n_enr;
   const int64_t rb = std::min<int64_t>(rows, rot_rows(N));
-  double *W, *T, *MVE, *S, *Hp, *E;
-  int *info;
+  const int64_t N2 = (int64_t)N * N;
+  double *W, *T, *MVE, *S, *Hp, *Li, *T1, *Qe, *R, *work;
+  int *iwork, *flag;
   if ((s = efe_ws(c, 5, (size_t)rows * N * 8, (void **)&W))) return s;
   if ((s = efe_ws(c, 3, (size_t)rb * N * 8, (void **)&T))) return s;
   if ((s = efe_ws(c, 6, (size_t)std::max<int64_t>(ne, 1) * N * 8, (void **)&MVE))) return s;
-  if ((s = efe_ws(c, 10, (size_t)(2 * (int64_t)N * N + N) * 8 + 64, (void **)&S))) return s;
-  Hp = S + (int64_t)N * N;
-  E = Hp + (int64_t)N * N;
-  info = (int *)(E + N);
+  if ((s = efe_ws(c, 10, (size_t)6 * N2 * 8 + 256, (void **)&S))) return s;
+  Hp = S + N2;
+  Li = Hp + N2;
+  T1 = Li + N2;
+  Qe = T1 + N2;
+  R = Qe + N2;
+  flag = (int *)(R + N2);
+  if ((s = efe_ws(c, 13, efe_syev_work(N) * 8, (void **)&work))) return s;
+  if ((s = efe_ws(c, 14, efe_syev_iwork(N) * sizeof(int), (void **)&iwork))) return s;
   const int t_rr = efe_timer_begin(c, EFE_T_RR);
   // W = H V, chunk by chunk
   for (int32_t j0 = 0; j0 < N; j0 += EFE_COL_CHUNK) {
@@ -103,44 +86,48 @@ extern "C" efe_status efe_rayleigh_ritz(efe_ctx *c, double *V, int32_t N, int64_
                                   EFE_FP64)))
       return s;
   }
-  // S = V^T M V, Hp = V^T W: tall-skinny products (N x N from all rows) by
-  // the split-K Gram kernel; a library GEMM without split-K leaves most of
-  // the chip idle at this shape
-  HIPCHK(c, hipMemsetAsync(S, 0, (size_t)2 * N * N * 8, c->stream));
-  if ((s = efe_gram(c, N, N, nn, 1.0, V, ld, V, ld, c->d_m_int, S, N))) return s;
+  // S = V^T M V, Hp = V^T W: tall-skinny products (N x N from all rows), the
+  // sum over rows split across work-groups so that the launch fills the
+  // chip; both are symmetric (H^E is), so only the upper triangle is formed
+  HIPCHK(c, hipMemsetAsync(S, 0, (size_t)2 * N2 * 8, c->stream));
+  if ((s = efe_gram_sym(c, N, nn, V, ld, V, ld, S, N, c->d_m_int))) return s;
   if (ne) {
-    if ((s = efe_gemm(c, false, false, ne, N, ne, 1.0, c->d_Mee, ne, V + nn * ld, ld, 0.0, MVE, N)))
+    if ((s = efe_dgemm(c, false, false, ne, N, ne, 1.0, c->d_Mee, ne, V + nn * ld, ld, 0.0, MVE,
+                       N)))
       return s;
-    if ((s = efe_gram(c, N, N, ne, 1.0, V + nn * ld, ld, MVE, N, nullptr, S, N))) return s;
+    if ((s = efe_gram_sym(c, N, ne, V + nn * ld, ld, MVE, N, S, N))) return s;
   }
-  if ((s = efe_gram(c, N, N, nn, 1.0, V, ld, W, N, nullptr, Hp, N))) return s;
-  if (ne && (s = efe_gram(c, N, N, ne, 1.0, V + nn * ld, ld, W + nn * N, N, nullptr, Hp, N)))
-    return s;
-  // Hp R = S R Lambda; the symmetric matrices read the same in either
-  // storage order; R comes back column-major in Hp, i.e. as R^T row-major
-  if (rocsolver_dsygvd(h, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_upper, N, Hp, N,
-                       S, N, lambda, E, info) != rocblas_status_success)
-    EFE_FAIL(c, EFE_EHIP, "rocsolver_dsygvd failed");
-  int hinfo = 0;
-  HIPCHK(c, hipMemcpyAsync(&hinfo, info, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  if ((s = efe_gram_sym(c, N, nn, V, ld, W, N, Hp, N))) return s;
+  if (ne && (s = efe_gram_sym(c, N, ne, V + nn * ld, ld, W + nn * N, N, Hp, N))) return s;
+  if ((s = efe_mirror_upper(c, N, S, N)) || (s = efe_mirror_upper(c, N, Hp, N))) return s;
+  // S = L L^T; Hp <- L^-1 Hp L^-T
+  HIPCHK(c, hipMemsetAsync(flag, 0, sizeof(int), c->stream));
+  if ((s = efe_potrf(c, N, S, N, flag))) return s;
+  int hflag = 0;
+  HIPCHK(c, hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  if (hinfo > N) EFE_FAIL(c, EFE_ENUMERIC, "overlap of the block is not positive definite");
-  if (hinfo) EFE_FAIL(c, EFE_ENUMERIC, "dense eigensolve did not converge");
+  if (hflag) EFE_FAIL(c, EFE_ENUMERIC, "overlap of the block is not positive definite");
+  if ((s = efe_trtri_lower(c, N, S, N, Li, N))) return s;
+  if ((s = efe_dgemm(c, false, false, N, N, N, 1.0, Li, N, Hp, N, 0.0, T1, N))) return s;
+  if ((s = efe_dgemm(c, false, true, N, N, N, 1.0, T1, N, Li, N, 0.0, Hp, N))) return s;
+  // Hp = Q Lambda Q^T; R = L^-T Q
+  if ((s = efe_syev_jacobi(c, N, Hp, N, lambda, Qe, work, iwork, &c->rr_sweeps))) return s;
+  if ((s = efe_dgemm(c, true, false, N, N, N, 1.0, Li, N, Qe, N, 0.0, R, N))) return s;
   // V <- V R, W <- W R, row block by row block through T
   for (int64_t r0 = 0; r0 < rows; r0 += rb) {
     const int64_t nr = std::min<int64_t>(rb, rows - r0);
-    if ((s = efe_gemm(c, false, true, nr, N, N, 1.0, V + r0 * ld, ld, Hp, N, 0.0, T, N))) return s;
+    if ((s = efe_dgemm(c, false, false, nr, N, N, 1.0, V + r0 * ld, ld, R, N, 0.0, T, N))) return s;
     k_copy_masked<<<cdiv(nr * N, 256), 256, 0, c->stream>>>(r0, nn, nr, N, c->d_minv, T, V + r0 * ld,
                                                            ld);
     if (resnorm) {
-      if ((s = efe_gemm(c, false, true, nr, N, N, 1.0, W + r0 * N, N, Hp, N, 0.0, T, N))) return s;
+      if ((s = efe_dgemm(c, false, false, nr, N, N, 1.0, W + r0 * N, N, R, N, 0.0, T, N))) return s;
       k_copy_masked<<<cdiv(nr * N, 256), 256, 0, c->stream>>>(r0, nn, nr, N, c->d_minv, T,
                                                              W + r0 * N, N);
     }
   }
   if (resnorm) {
-    if (ne && (s = efe_gemm(c, false, false, ne, N, ne, 1.0, c->d_Mee, ne, V + nn * ld, ld, 0.0,
-                            MVE, N)))
+    if (ne && (s = efe_dgemm(c, false, false, ne, N, ne, 1.0, c->d_Mee, ne, V + nn * ld, ld, 0.0,
+                             MVE, N)))
       return s;
     HIPCHK(c, hipMemsetAsync(resnorm, 0, N * 8, c->stream));
     dim3 blkd(64, 4), grd((unsigned)std::min<int64_t>(cdiv(rows, 4), 4096), cdiv(N, 64));
