@@ -8,6 +8,8 @@ import ctypes
 import numpy as np
 import pytest
 
+from tolerances import filter_tol
+
 from paper_2607_06848_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
@@ -57,7 +59,7 @@ def test_noalloc_filter_matches_filter(name):
         torch.cuda.synchronize()
         r, g = ref.cpu().numpy(), got.cpu().numpy()
         err = np.abs(g - r).max() / np.abs(r).max()
-        tol = 1e-11 + 1e-14 * s.tilde_condition()
+        tol = filter_tol(m, s.tilde_condition())
         _say(name, ncols, "columns: rel diff to efe_cheb_filter", err, "tol", tol)
         assert err < tol
     ctx.close()
