@@ -610,9 +610,38 @@ __global__ __launch_bounds__(256) void k_expand_init(int64_t n_nodes, int ncols,
   const int npr = (ncols + 1) / 2;
   const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (idx >= n_nodes * npr) return;
-  const int64_t node = idx / npr;
-  const int c0 = 2 * (int)(idx % npr);
+  int64_t node;
+  int c0;
+  if (n_nodes * npr < (1ll << 31)) {          // 32-bit division where it fits
+    node = (uint32_t)idx / (uint32_t)npr;
+    c0 = 2 * (int)((uint32_t)idx - (uint32_t)node * (uint32_t)npr);
+  } else {
+    node = idx / npr;
+    c0 = 2 * (int)(idx % npr);
+  }
   const bool two = c0 + 1 < ncols;
+  const int64_t o = node * ldy + c0;
+  // pairs by 16-byte accesses when the layout allows it (vec: even ld,
+  // aligned arrays), else element by element
+  auto ld2 = [&](const double *p) -> double2 {
+    if (vec && two) return *reinterpret_cast<const double2 *>(p + o);
+    double2 r;
+    r.x = p[o];
+    r.y = two ? p[o + 1] : 0.0;
+    return r;
+  };
+  // the streamed rows first, so that they are in flight while the
+  // projector entries (two dependent loads each) come in
+  double2 z1 = make_double2(0.0, 0.0), z2 = z1, g = z1;
+  double cl0 = 0.0, cl1 = 0.0;
+  if (e.Z1) z1 = ld2(e.Z1);
+  if (e.Z2) z2 = ld2(e.Z2);
+  if (e.G) {
+    g = ld2(e.G);
+    cl0 = e.Cl[c0];
+    cl1 = two ? e.Cl[c0 + 1] : 0.0;
+  }
+  const bool inner = minv[node] != 0.0;
   double a0 = 0.0, a1 = 0.0;
   if (kbnm_ptr) {
     const int32_t e0 = kbnm_ptr[node], e1 = kbnm_ptr[node + 1];
@@ -623,34 +652,16 @@ __global__ __launch_bounds__(256) void k_expand_init(int64_t n_nodes, int ncols,
       if (two) a1 += p * w[1];
     }
   }
-  const int64_t o = node * ldy + c0;
-  const bool inner = minv[node] != 0.0;
-  // pairs by 16-byte accesses when the layout allows it (vec: even ld,
-  // aligned arrays), else element by element
-  auto ld2 = [&](const double *p) -> double2 {
-    if (vec && two) return *reinterpret_cast<const double2 *>(p + o);
-    double2 r;
-    r.x = p[o];
-    r.y = two ? p[o + 1] : 0.0;
-    return r;
-  };
   double2 v;
-  v.x = e.alpha * a0;
-  v.y = e.alpha * a1;
+  v.x = e.alpha * (a0 + g.x * cl0);
+  v.y = e.alpha * (a1 + g.y * cl1);
   if (e.Z1) {
-    const double2 z = ld2(e.Z1);
-    v.x += e.beta * z.x;
-    v.y += e.beta * z.y;
+    v.x += e.beta * z1.x;
+    v.y += e.beta * z1.y;
   }
   if (e.Z2) {
-    const double2 z = ld2(e.Z2);
-    v.x += e.gamma * z.x;
-    v.y += e.gamma * z.y;
-  }
-  if (e.G) {
-    const double2 g = ld2(e.G);
-    v.x += e.alpha * g.x * e.Cl[c0];
-    v.y += e.alpha * g.y * (two ? e.Cl[c0 + 1] : 0.0);
+    v.x += e.gamma * z2.x;
+    v.y += e.gamma * z2.y;
   }
   if (!inner) v.x = v.y = 0.0;
   if (vec && two) {

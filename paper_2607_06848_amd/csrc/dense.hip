@@ -421,19 +421,18 @@ efe_status efe_trtri_lower(efe_ctx *c, int64_t n, const double *L, int64_t ldl, 
 // off-diagonal part is below tol of the whole.
 constexpr int JB = 32, J2 = 2 * JB;
 
-// pairs of one round, listed on the host in the same order as the kernels
-static void round_pairs(int nb, int round, std::vector<int> &P, std::vector<int> &Q) {
-  // circle method: block 0 stays, blocks 1 .. nb-1 rotate one place per
-  // round; position k meets position nb-1-k
-  const int m = nb - 1;
-  P.clear();
-  Q.clear();
-  for (int k = 0; k < nb / 2; ++k) {
-    const int a = k == 0 ? 0 : 1 + (round + k - 1) % m;
-    const int b = k == 0 ? 1 + (round + m - 1) % m : 1 + (round + m - k - 1) % m;
-    P.push_back(std::min(a, b));
-    Q.push_back(std::max(a, b));
-  }
+// the pairs of every round of a sweep: round r, position k -> (p, q), by
+// the circle method (block 0 stays, blocks 1 .. nb-1 rotate one place per
+// round; position k meets position nb-1-k)
+__global__ void k_round_pairs(int nb, int *__restrict__ pairs) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int npair = nb / 2, m = nb - 1;
+  if (e >= m * npair) return;
+  const int r = e / npair, k = e % npair;
+  const int a = k == 0 ? 0 : 1 + (r + k - 1) % m;
+  const int b = k == 0 ? 1 + (r + m - 1) % m : 1 + (r + m - k - 1) % m;
+  pairs[2 * e] = min(a, b);
+  pairs[2 * e + 1] = max(a, b);
 }
 
 // the 2 JB x 2 JB subproblem of pair k: eigenvectors into U[k] (row-major
@@ -614,6 +613,24 @@ __global__ void k_pad_sym(int64_t n, int64_t np, const double *__restrict__ H, i
   A[e] = v;
 }
 
+// ascending order of the diagonal of the np x np A (ties by index): the
+// first n values into w, their indices into ord
+__global__ void k_sort_diag(int64_t np, const double *__restrict__ A, int64_t n,
+                            double *__restrict__ w, int *__restrict__ ord) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= np) return;
+  const double di = A[i * (np + 1)];
+  int64_t rank = 0;
+  for (int64_t j = 0; j < np; ++j) {
+    const double dj = A[j * (np + 1)];
+    rank += (dj < di) || (dj == di && j < i);
+  }
+  if (rank < n) {
+    w[rank] = di;
+    ord[rank] = (int)i;
+  }
+}
+
 // Q[r][i] = V[r][ord[i]] for r, i < n
 __global__ void k_gather_cols(int64_t n, const double *__restrict__ V, int64_t ldv,
                               const int *__restrict__ ord, double *__restrict__ Q, int64_t ldq) {
@@ -637,7 +654,7 @@ size_t efe_syev_work(int64_t n) {
 
 size_t efe_syev_iwork(int64_t n) {
   const int nb = jacobi_blocks(n);
-  return (size_t)std::max<int64_t>((int64_t)(nb - 1) * nb, n);
+  return (size_t)((int64_t)(nb - 1) * nb + n);
 }
 
 // Eigen-decomposition H = Q diag(w) Q^T of the symmetric n x n matrix H.
@@ -665,17 +682,7 @@ efe_status efe_syev_jacobi(efe_ctx *c, int64_t n, const double *H, int64_t ldh, 
   k_pad_sym<<<cdiv(np * np, 256), 256, 0, c->stream>>>(n, np, H, ldh, top, A);
   k_eye<<<cdiv(np * np, 256), 256, 0, c->stream>>>(np, V, np);
   // the pair lists of all rounds of a sweep
-  std::vector<int> allp;
-  std::vector<int> P, Qv;
-  for (int r = 0; r < nb - 1; ++r) {
-    round_pairs(nb, r, P, Qv);
-    for (int k = 0; k < npair; ++k) {
-      allp.push_back(P[k]);
-      allp.push_back(Qv[k]);
-    }
-  }
-  HIPCHK(c, hipMemcpyAsync(iwork, allp.data(), allp.size() * sizeof(int), hipMemcpyHostToDevice,
-                           c->stream));
+  k_round_pairs<<<cdiv((int64_t)(nb - 1) * npair, 256), 256, 0, c->stream>>>(nb, iwork);
   int sw = 0;
   double prev = INFINITY;
   for (; sw < 40; ++sw) {
@@ -702,21 +709,10 @@ efe_status efe_syev_jacobi(efe_ctx *c, int64_t n, const double *H, int64_t ldh, 
   }
   if (sweeps_out) *sweeps_out = sw;
   if (sw == 40) EFE_FAIL(c, EFE_ENOTCONV, "block Jacobi did not converge in 40 sweeps");
-  // eigenvalues: the diagonal; ascending order by a host sort of n values
-  std::vector<double> d(np);
-  HIPCHK(c, hipMemcpy2DAsync(d.data(), 8, A, (np + 1) * 8, 8, np, hipMemcpyDeviceToHost,
-                             c->stream));
-  HIPCHK(c, hipStreamSynchronize(c->stream));
-  std::vector<int> ord(np);
-  std::iota(ord.begin(), ord.end(), 0);
-  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return d[a] < d[b]; });
-  std::vector<double> ws(n);
-  for (int64_t i = 0; i < n; ++i) ws[i] = d[ord[i]];
-  HIPCHK(c, hipMemcpyAsync(w, ws.data(), n * 8, hipMemcpyHostToDevice, c->stream));
-  HIPCHK(c, hipMemcpyAsync(iwork, ord.data(), n * sizeof(int), hipMemcpyHostToDevice, c->stream));
-  // Q[:, i] = V[:n, ord[i]]
-  k_gather_cols<<<cdiv(n * n, 256), 256, 0, c->stream>>>(n, V, np, iwork, Q, n);
-  HIPCHK(c, hipStreamSynchronize(c->stream));   // host vectors go out of scope
+  // eigenvalues: the diagonal in ascending order; Q[:, i] = V[:n, ord[i]]
+  int *ord = iwork + (int64_t)(nb - 1) * 2 * npair;
+  k_sort_diag<<<cdiv(np, 256), 256, 0, c->stream>>>(np, A, n, w, ord);
+  k_gather_cols<<<cdiv(n * n, 256), 256, 0, c->stream>>>(n, V, np, ord, Q, n);
   HIPCHK(c, hipGetLastError());
   return EFE_OK;
 }
