@@ -128,7 +128,9 @@ class EFESystem:
 
     ``params`` keys: xyz (natoms, 3), Z (natoms), enr_lmax, enr_alpha,
     enr_rcut, enr_t, kb_width, kb_D, kb_rcut (kb_width <= 0 disables the
-    projectors)."""
+    projectors); optional enr_table (radial.enrichment_tables: tabulated
+    single-atom radial functions with their own cutoffs replace the Gaussian;
+    enr_rcut must then cover the largest cutoff)."""
 
     def __init__(self, mesh, params):
         self.mesh = mesh
@@ -158,10 +160,15 @@ class EFESystem:
         self.gphi = []
         if self.nf == 0:
             return
+        table = p.get("enr_table")
         for I in range(self.natoms):
             cells = support_cells(mesh, self.xyz[I], p["enr_rcut"])
-            phi, g = enrichment_raw(mesh, self.xyz[I], cells, self.lmax,
-                                    p["enr_alpha"], p["enr_rcut"], p["enr_t"])
+            if table is None:
+                phi, g = enrichment_raw(mesh, self.xyz[I], cells, self.lmax,
+                                        p["enr_alpha"], p["enr_rcut"], p["enr_t"])
+            else:
+                from . import radial
+                phi, g = radial.enrichment_tabulated(mesh, self.xyz[I], cells, self.lmax, table)
             norm2 = np.einsum('cqk,cqk,q->k', phi, phi, mesh.W3)
             nu = 1.0 / np.sqrt(norm2)
             self.supp.append(cells)
