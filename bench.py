@@ -109,17 +109,20 @@ def cpu_baseline(w):
 
 
 def profile_applies(w, prec, k):
-    """A short program for hardware-counter runs: K H^E applies of the
-    workload's block under the local pseudopotential, then one plain device
-    copy of 1 GiB."""
+    """A short program for hardware-counter runs: K H^E applies of one column
+    chunk of the workload's block (its first min(N, 160) columns: the width
+    one cell-GEMM launch takes) under the local pseudopotential, then one
+    plain device copy of 1 GiB."""
     import torch
     from paper_2607_06848_amd import efe
     from paper_2607_06848_amd import workloads as wl
     ctx = efe.Context(w)
     vq = ctx.local_potential()
     ctx.set_potential(vq, precisions=(1 << efe.EFE_FP32) | (1 << efe.EFE_BF16))
-    N = w["nvec"]
-    X = torch.from_numpy(wl.random_block(ctx.rows, N, w["v0_seed"])).cuda()
+    N = min(w["nvec"], COL_CHUNK)
+    X = torch.empty(ctx.rows, N, dtype=torch.float64, device="cuda")
+    for r0, blk in wl.random_block_rows(ctx.rows, N, w["v0_seed"], 1 << 18):
+        X[r0:r0 + len(blk)].copy_(torch.from_numpy(blk))
     Y = torch.empty_like(X)
     torch.cuda.synchronize()
     ctx.timing(True)
@@ -202,7 +205,8 @@ def time_to_scf(args, w, new_run, on_pass):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         fb, fac = mdl.apply(ctx) if mdl is not None else ctx.density_guess(None)
-        hist = efe.scf_run(ctx, V, lam, v0, deg, tol=1e-5, max_iter=args.max_scf_steps,
+        hist = efe.scf_run(ctx, V, lam, v0, deg, tol=args.scf_tol, rho_tol=args.scf_tol,
+                           max_iter=args.max_scf_steps,
                            prec=prec_k, passes_first=args.passes_first, passes=1,
                            tau=args.tau, max_passes=args.max_passes, kerker_k0=args.kerker,
                            progress=on_pass,
@@ -216,15 +220,16 @@ def time_to_scf(args, w, new_run, on_pass):
         ctx.close()
         res[name] = {"seconds": t_scf, "steps": len(hist),
                      "filter_passes": sum(h["passes"] for h in hist), "E_Ha": hist[-1]["E"],
-                     "converged": len(hist) > 1 and abs(hist[-1]["dE"]) / len(w["xyz"]) < 1e-5
-                     and hist[-1]["drho"] / hist[-1]["n_el"] < 1e-5,
+                     "converged": len(hist) > 1
+                     and abs(hist[-1]["dE"]) / len(w["xyz"]) < args.scf_tol
+                     and hist[-1]["drho"] / hist[-1]["n_el"] < args.scf_tol,
                      "last_dE_per_atom": abs(hist[-1]["dE"]) / len(w["xyz"]),
                      "last_drho_per_electron": hist[-1]["drho"] / hist[-1]["n_el"],
                      "guess": "learned" if mdl is not None and not fb else "superposition",
                      "filter_precision": "fp64" if prec_k == 0 else "fp32",
                      "max_occ_res": [h["max_occ_res"] for h in hist],
                      "E_per_step": [h["E"] for h in hist],
-                     "tau": args.tau, "kerker_k0": args.kerker}
+                     "tau": args.tau, "kerker_k0": args.kerker, "scf_tol": args.scf_tol}
         log(f"SCF {name}: {len(hist)} steps, {t_scf:.1f} s, E {hist[-1]['E']:.8f}")
     for other in ("fp32_learned", "fp64_learned", "fp32_sad"):
         if other in res and "fp64_sad" in res:
@@ -247,7 +252,7 @@ def main():
                     help="time-to-SCF runs, comma separated <fp64|fp32>_<sad|learned>")
     ap.add_argument("--profile-applies", type=int, default=0, metavar="K",
                     help="profiling mode: set up the workload with its local pseudopotential, "
-                         "run K H^E applies of the N-vector block in --prec, copy a 1 GiB buffer "
+                         "run K H^E applies of one 160-column chunk in --prec, copy a 1 GiB buffer "
                          "once (a plain copy of known size for counter calibration), print "
                          "timings and exit without the JSON line")
     ap.add_argument("--prec-error", action="store_true",
@@ -263,6 +268,9 @@ def main():
                     help="time-to-SCF runs: minimum passes of the first SCF step")
     ap.add_argument("--kerker", type=float, default=0.0,
                     help="time-to-SCF runs: Kerker k0 of the mixing (0: plain Anderson)")
+    ap.add_argument("--scf-tol", type=float, default=1e-5,
+                    help="time-to-SCF runs: stop when |dE| per atom and the density change "
+                         "per electron are both below this")
     ap.add_argument("--max-scf-steps", type=int, default=60,
                     help="step cap of each time-to-SCF run (a capped run reports converged: false)")
     ap.add_argument("--scf-only", action="store_true",

@@ -71,7 +71,15 @@ typedef struct {
  *                cutoff h ending at enr_rcut with smoothness enr_t
  *                (Eq. eqnCutoffProperties); enr_lmax < 0: plain CFE
  *   rho_alpha    exponent of the Gaussian isolated-atom density (Sec. III.C)
- * xyz and Z are host arrays read during efe_setup_mesh only. */
+ *   enr_tab_n    > 0: pristine enrichment (Sec. II.B) instead of the Gaussian:
+ *                S_lm(x-R) f_l(r) h(r) with f_l = R_l / r^l of the isolated
+ *                atom's lowest level of angular momentum l (efe_radial_atom),
+ *                tabulated at r = i enr_tab_dr, i < enr_tab_n, as
+ *                enr_tab[(2 l) n + i] = f_l, enr_tab[(2 l + 1) n + i] = f_l'
+ *                (l <= enr_lmax), cubic Hermite interpolation, zero beyond
+ *                the table; h ends at enr_tab_rc[l] with smoothness enr_t;
+ *                enr_rcut (the support radius) must cover every enr_tab_rc[l]
+ * xyz, Z and enr_tab are host arrays read during efe_setup_mesh only. */
 typedef struct {
   int32_t natoms;
   const double *xyz;
@@ -81,6 +89,10 @@ typedef struct {
   int32_t enr_lmax;
   double enr_alpha, enr_rcut, enr_t;
   double rho_alpha;
+  int32_t enr_tab_n;
+  double enr_tab_dr;
+  const double *enr_tab;
+  double enr_tab_rc[3];
 } efe_system_desc;
 
 /* Build the mesh tables, the enrichment and projector data and the overlap
@@ -89,6 +101,48 @@ typedef struct {
  * hipStream_t (NULL: default stream).  On success *out owns device memory. */
 efe_status efe_setup_mesh(const efe_mesh_desc *mesh, const efe_system_desc *sys,
                           void *stream, efe_ctx **out);
+
+/* Radial Kohn-Sham problem of one isolated atom of the synthetic
+ * pseudopotential (Sec. II.B: the pristine enrichment functions are the
+ * isolated atom's eigenfunctions, a radial part from a 1-D problem times a
+ * real spherical harmonic).  u = r R on r_i = i h (i = 1 .. n), zero at 0 and
+ * (n+1) h; channel l: -(u_{i+1} - 2u_i + u_{i-1})/(2h^2) + (l(l+1)/(2r^2) +
+ * v_eff) u, plus the s projector D |beta><beta| in channel 0; v_eff = local
+ * pseudopotential + Hartree (same three-point rule, w = r v_H, w'' = -4 pi r
+ * rho) + PW92; Fermi occupations (kT) of the 2(2l+1)-fold levels for Z[atom]
+ * electrons; rho_in <- rho_in + mix_beta (rho_out - rho_in) from the Gaussian
+ * atomic density until sqrt(4 pi h sum r^2 (rho_out - rho_in)^2) < tol.
+ * Then, per l, the lowest level's table f_l = R/r^l and r0 by the three rules
+ * of Sec. II.B (at or beyond the last turning point of u, truncated norm
+ * within 5e-3 of one, |dR/dr| < 5e-3; at most 10 bohr) with the cutoff's
+ * smoothness sys->enr_t.  Outputs (device, written on `stream`):
+ *   eps[(lmax+1) nstates], occ[...] (electrons per level, with 2(2l+1)),
+ *   u[(l nstates + k) n + i] (h sum u^2 = 1, largest |u| positive),
+ *   rho[n] (the last output density), r0[lmax+1],
+ *   tab[2(lmax+1)][n+1]: rows 2l, 2l+1 = f_l, f_l' at r = i h (i = 0..n),
+ *   the layout of efe_system_desc.enr_tab (cutoff radius r0 (1 + 1/t)).
+ * Allocates and frees its own device workspace; reads sys on the host.
+ * EFE_ENOTCONV when maxit iterations do not reach tol (outputs are those of
+ * the last iteration); messages through efe_last_error(NULL). */
+typedef struct {
+  int32_t n;          /* grid points */
+  double h;           /* spacing (bohr) */
+  int32_t lmax;       /* channels 0..lmax, lmax <= 2 */
+  int32_t nstates;    /* levels per channel, 1..8 */
+  double kT, mix_beta, tol;
+  int32_t maxit;
+} efe_radial_params;
+
+typedef struct {
+  int32_t iterations;
+  double residual;    /* last density residual */
+  double mu;          /* Fermi level */
+} efe_radial_report;
+
+efe_status efe_radial_atom(const efe_system_desc *sys, int32_t atom,
+                           const efe_radial_params *prm, void *stream, double *eps, double *u,
+                           double *occ, double *rho, double *r0, double *tab,
+                           efe_radial_report *rep);
 
 /* sizes[0..7] = rows, n_nodes, n_dof (interior nodes + enrichment), n_enr,
  * n_cells, n_qpts (n_cells * nq^3), natoms, nloc ((p+1)^3).  Host array. */

@@ -260,8 +260,14 @@ extern "C" efe_status efe_setup_mesh(const efe_mesh_desc *mesh, const efe_system
     if (mesh->ncell[d] < 1 || !(mesh->hi[d] > mesh->lo[d])) return EFE_EINVAL;
   if (sys->natoms < 0 || (sys->natoms > 0 && (!sys->xyz || !sys->Z))) return EFE_EINVAL;
   if (sys->enr_lmax > 2) return EFE_EINVAL;
-  if (sys->enr_lmax >= 0 && !(sys->enr_rcut > 0 && sys->enr_t > 0 && sys->enr_alpha > 0))
+  const bool tab = sys->enr_lmax >= 0 && sys->enr_tab_n > 0;
+  if (sys->enr_lmax >= 0 && !(sys->enr_rcut > 0 && sys->enr_t > 0 && (tab || sys->enr_alpha > 0)))
     return EFE_EINVAL;
+  if (tab) {
+    if (!sys->enr_tab || sys->enr_tab_n < 2 || !(sys->enr_tab_dr > 0)) return EFE_EINVAL;
+    for (int l = 0; l <= sys->enr_lmax; ++l)
+      if (!(sys->enr_tab_rc[l] > 0) || sys->enr_tab_rc[l] > sys->enr_rcut) return EFE_EINVAL;
+  }
   if (sys->kb_width > 0 && !(sys->kb_rcut > 0)) return EFE_EINVAL;
   if (!(sys->loc_rc > 0) || !(sys->loc_rg > 0)) return EFE_EINVAL;
 
@@ -304,6 +310,12 @@ extern "C" efe_status efe_setup_mesh(const efe_mesh_desc *mesh, const efe_system
   c->enr_rcut = sys->enr_rcut;
   c->enr_t = sys->enr_t;
   c->rho_alpha = sys->rho_alpha;
+  if (tab) {
+    c->ntab = sys->enr_tab_n;
+    c->tab_dr = sys->enr_tab_dr;
+    for (int l = 0; l <= sys->enr_lmax; ++l) c->tab_rc[l] = sys->enr_tab_rc[l];
+    c->tab_host.assign(sys->enr_tab, sys->enr_tab + (size_t)2 * (sys->enr_lmax + 1) * c->ntab);
+  }
   c->nf = c->lmax < 0 ? 0 : (c->lmax + 1) * (c->lmax + 1);
   if (c->natoms == 0) c->nf = 0;
   c->n_enr = (int64_t)c->natoms * c->nf;
@@ -327,6 +339,7 @@ extern "C" efe_status efe_setup_mesh(const efe_mesh_desc *mesh, const efe_system
     std::vector<double> xyz = c->xyz, Zs = c->Z;
     TRY(upload(c, &c->d_xyz, xyz));
     TRY(upload(c, &c->d_Zs, Zs));
+    if (c->ntab > 0) TRY(upload(c, &c->d_enr_tab, c->tab_host));
     TRY(efe_build_reference(c));
 
     SupportTables E, K;

@@ -43,6 +43,11 @@ struct efe_ctx {
   std::vector<double> xyz, Z;
   double loc_rc, loc_amp, loc_rg, kb_width, kb_D, kb_rcut, enr_alpha, enr_rcut, enr_t,
       rho_alpha;
+  // tabulated radial enrichment (ntab = 0: Gaussian)
+  int ntab = 0;
+  double tab_dr = 0.0, tab_rc[3] = {0.0, 0.0, 0.0};
+  double *d_enr_tab = nullptr;
+  std::vector<double> tab_host;
 
   // support tables (host copies kept for efe_get_support)
   std::vector<int32_t> enr_ptr, enr_cells, kb_ptr, kb_cells;

@@ -312,28 +312,6 @@ __global__ __launch_bounds__(256) void k_nodes_to_quad(int nloc, int nqp, const 
   }
 }
 
-// PW92 LDA (unpolarized): energy per electron and potential
-__device__ inline void lda_pw92(double rho, double &exc, double &vxc) {
-  if (!(rho > 1e-14)) {
-    exc = 0.0;
-    vxc = 0.0;
-    return;
-  }
-  const double ex = -0.75 * cbrt(3.0 / M_PI) * cbrt(rho);
-  const double vx = 4.0 / 3.0 * ex;
-  const double rs = cbrt(3.0 / (4.0 * M_PI * rho));
-  const double A = 0.031091, a1 = 0.21370, b1 = 7.5957, b2 = 3.5876, b3 = 1.6382, b4 = 0.49294;
-  const double srs = sqrt(rs);
-  const double Q0 = -2.0 * A * (1.0 + a1 * rs);
-  const double Q1 = 2.0 * A * (b1 * srs + b2 * rs + b3 * rs * srs + b4 * rs * rs);
-  const double Q1p = A * (b1 / srs + 2.0 * b2 + 3.0 * b3 * srs + 4.0 * b4 * rs);
-  const double L = log1p(1.0 / Q1);
-  const double ec = Q0 * L;
-  const double dec = -2.0 * A * a1 * L - Q0 * Q1p / (Q1 * Q1 + Q1);
-  exc = ex + ec;
-  vxc = vx + ec - rs / 3.0 * dec;
-}
-
 // v_in = phi_at + phi_rem(q) + v_short + v_xc(rho_in)
 __global__ void k_veff(int64_t n, const double *__restrict__ rho, const double *__restrict__ phi_at,
                        const double *__restrict__ phiq, const double *__restrict__ vs,
@@ -1050,12 +1028,7 @@ extern "C" efe_status efe_scf_step(efe_ctx *c, double *V, int32_t N, int64_t ld,
   std::vector<int32_t> rel(cols.size());   // read by async copies until the sync below
   {
     const MeshGeo g = mesh_geo(c);
-    EnrParam e;
-    e.lmax = c->lmax;
-    e.nf = c->nf;
-    e.alpha = c->enr_alpha;
-    e.rc = c->enr_rcut;
-    e.t = c->enr_t;
+    const EnrParam e = enr_param(c);
     size_t done = 0;
     bool first = true;
     for (int32_t j0 = 0; j0 < N; j0 += EFE_COL_CHUNK) {

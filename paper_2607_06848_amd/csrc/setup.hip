@@ -904,16 +904,6 @@ efe_status efe_build_reference(efe_ctx *c) {
   return EFE_OK;
 }
 
-static EnrParam enr_param(const efe_ctx *c) {
-  EnrParam e;
-  e.lmax = c->lmax;
-  e.nf = c->nf;
-  e.alpha = c->enr_alpha;
-  e.rc = c->enr_rcut;
-  e.t = c->enr_t;
-  return e;
-}
-
 efe_status efe_build_enrichment(efe_ctx *c) {
   efe_status s;
   const MeshGeo g = mesh_geo(c);

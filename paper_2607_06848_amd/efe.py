@@ -37,7 +37,9 @@ class SystemDesc(ctypes.Structure):
                 ("kb_D", ctypes.c_double), ("kb_rcut", ctypes.c_double),
                 ("enr_lmax", ctypes.c_int32), ("enr_alpha", ctypes.c_double),
                 ("enr_rcut", ctypes.c_double), ("enr_t", ctypes.c_double),
-                ("rho_alpha", ctypes.c_double)]
+                ("rho_alpha", ctypes.c_double), ("enr_tab_n", ctypes.c_int32),
+                ("enr_tab_dr", ctypes.c_double), ("enr_tab", c_double_p),
+                ("enr_tab_rc", ctypes.c_double * 3)]
 
 
 class ChebParams(ctypes.Structure):
@@ -71,6 +73,18 @@ class ScfReport(ctypes.Structure):
         return {n: getattr(self, n) for n, _ in self._fields_}
 
 
+class RadialParams(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("h", ctypes.c_double), ("lmax", ctypes.c_int32),
+                ("nstates", ctypes.c_int32), ("kT", ctypes.c_double),
+                ("mix_beta", ctypes.c_double), ("tol", ctypes.c_double),
+                ("maxit", ctypes.c_int32)]
+
+
+class RadialReport(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("residual", ctypes.c_double),
+                ("mu", ctypes.c_double)]
+
+
 class EFEError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{STATUS.get(status, status)}: {msg}")
@@ -84,6 +98,9 @@ _SIGS = {
     "efe_setup_mesh": (ctypes.c_int32, [ctypes.POINTER(MeshDesc), ctypes.POINTER(SystemDesc),
                                         ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
     "efe_get_sizes": (ctypes.c_int32, [ctypes.c_void_p, c_int64_p]),
+    "efe_radial_atom": (ctypes.c_int32, [ctypes.POINTER(SystemDesc), ctypes.c_int32,
+                                         ctypes.POINTER(RadialParams), ctypes.c_void_p]
+                        + [ctypes.c_void_p] * 6 + [ctypes.POINTER(RadialReport)]),
     "efe_enrichment_amplification": (ctypes.c_int32, [ctypes.c_void_p, c_double_p]),
     "efe_get_coupling": (ctypes.c_int32, [ctypes.c_void_p, c_int64_p, c_int64_p]),
     "efe_get_tables": (ctypes.c_int32, [ctypes.c_void_p, c_int32_p, c_int32_p, c_int32_p,
@@ -193,6 +210,17 @@ class Context:
                   "enr_rcut", "enr_t", "rho_alpha"):
             setattr(sd, k, float(w.get(k, 0.0)))
         sd.enr_lmax = int(w.get("enr_lmax", -1))
+        tab = w.get("enr_table")
+        if tab is not None and sd.enr_lmax >= 0:
+            # rows 2l, 2l+1: f_l and f_l' (l <= enr_lmax)
+            L_ = sd.enr_lmax + 1
+            self._tab = np.ascontiguousarray(np.stack(
+                [np.asarray(tab[k][l], np.float64) for l in range(L_) for k in ("f", "df")]))
+            sd.enr_tab_n = self._tab.shape[1]
+            sd.enr_tab_dr = float(tab["dr"])
+            sd.enr_tab = self._tab.ctypes.data_as(c_double_p)
+            for l in range(L_):
+                sd.enr_tab_rc[l] = float(tab["rc"][l])
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
         self.stream = stream
@@ -492,6 +520,51 @@ def efe_mlp_adam(params, grads, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8
 
 
 # module-level names of the C entry points
+def radial_atom(w, n=2000, h=0.02, lmax=1, nstates=2, kT=500 * 3.166811563e-6, beta=0.5,
+                tol=1e-10, maxit=300, atom=0, stream=None):
+    """efe_radial_atom for atom `atom` of workload w: the isolated atom's
+    levels, radial functions, density, r0 and enrichment table on the GPU;
+    returns numpy arrays (and the table in the form Context accepts as
+    w["enr_table"])."""
+    import torch
+    xyz = np.ascontiguousarray(np.asarray(w["xyz"], np.float64).reshape(-1, 3))
+    Z = np.ascontiguousarray(np.asarray(w.get("Zs", np.full(len(xyz), w.get("Z", 0.0))),
+                                        np.float64))
+    sd = SystemDesc()
+    sd.natoms = xyz.shape[0]
+    sd.xyz = xyz.ctypes.data_as(c_double_p)
+    sd.Z = Z.ctypes.data_as(c_double_p)
+    for k in ("loc_rc", "loc_amp", "loc_rg", "kb_width", "kb_D", "kb_rcut", "enr_alpha",
+              "enr_rcut", "enr_t", "rho_alpha"):
+        setattr(sd, k, float(w.get(k, 0.0)))
+    sd.enr_lmax = int(w.get("enr_lmax", -1))
+    pr = RadialParams(int(n), float(h), int(lmax), int(nstates), float(kT), float(beta),
+                      float(tol), int(maxit))
+    nl = (lmax + 1) * nstates
+    dev = dict(dtype=torch.float64, device="cuda")
+    eps, occ = torch.zeros(nl, **dev), torch.zeros(nl, **dev)
+    u = torch.zeros(nl, n, **dev)
+    rho = torch.zeros(n, **dev)
+    r0 = torch.zeros(lmax + 1, **dev)
+    tab = torch.zeros(2 * (lmax + 1), n + 1, **dev)
+    rep = RadialReport()
+    st = lib().efe_radial_atom(ctypes.byref(sd), int(atom), ctypes.byref(pr),
+                               _stream(stream), _ptr(eps), _ptr(u), _ptr(occ),
+                               _ptr(rho), _ptr(r0), _ptr(tab), ctypes.byref(rep))
+    if st != 0:
+        raise EFEError(st, lib().efe_last_error(None).decode())
+    torch.cuda.synchronize()
+    t = float(w.get("enr_t", 0.33))
+    T = tab.cpu().numpy()
+    R0 = r0.cpu().numpy()
+    return dict(eps=eps.cpu().numpy().reshape(lmax + 1, nstates),
+                occ=occ.cpu().numpy().reshape(lmax + 1, nstates),
+                u=u.cpu().numpy().reshape(lmax + 1, nstates, n), rho=rho.cpu().numpy(), r0=R0,
+                iterations=rep.iterations, residual=rep.residual, mu=rep.mu,
+                table=dict(f=T[0::2], df=T[1::2], dr=float(h), r0=R0, rc=R0 * (1.0 + 1.0 / t),
+                           t=t))
+
+
 def efe_setup_mesh(workload, stream=None):
     return Context(workload, stream)
 

@@ -52,7 +52,8 @@ def test_setup_error_without_gpu_is_reported():
 # the binding's ctypes mirrors of the header's structs, field by field
 STRUCTS = {"efe_mesh_desc": "MeshDesc", "efe_system_desc": "SystemDesc",
            "efe_cheb_params": "ChebParams", "efe_scf_params": "ScfParams",
-           "efe_scf_report": "ScfReport"}
+           "efe_scf_report": "ScfReport", "efe_radial_params": "RadialParams",
+           "efe_radial_report": "RadialReport"}
 
 
 def test_struct_layouts_match_the_header(tmp_path):
