@@ -119,14 +119,10 @@ __global__ __launch_bounds__(256) void k_pre(int64_t n_nodes, int ncols, const d
 }
 
 // ------------------------------------------------------------------ cell GEMM
-// Cell GEMM, second form: one work-group = one cell of the colour and a
-// part of its row blocks, all (up to 160) columns.  Each wave keeps RBW row
-// blocks x CBM column blocks of accumulators, so every cell-matrix fragment
-// loaded from memory feeds CBM MFMAs.  The gathered block of Xh streams
-// through LDS in 16-row chunks, double buffered; the cell-matrix fragments
-// of the next chunk are loaded into registers while the current chunk is
-// multiplied.  T = double (v_mfma_f64_16x16x4) or float
-// (v_mfma_f32_16x16x4, FP32 accumulation).
+// Matrix-core operations of the cell GEMM per element type: the operand
+// fragments and accumulator layout of v_mfma_f64_16x16x4 (double) and
+// v_mfma_f32_16x16x4 (float, FP32 accumulation), and the LDS row strides of
+// the gathered block.
 template <typename T>
 struct CellMfma;
 template <>
