@@ -34,7 +34,7 @@ sys.path.insert(0, ROOT)
 PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15, "hbm": 8.0e12}
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
 COL_CHUNK = 160   # column chunk of the filter and of one cell GEMM launch
-CELL_KERNEL = {"fp64": "k_cell3<double, 1, 10, true>", "fp32": "k_cell3<float, 1, 10, true>",
+CELL_KERNEL = {"fp64": "k_cell3<double, 1, 10, true>", "fp32": "k_cell3<float, 2, 10, true>",
                "bf16": "k_cell_bf16<32>"}
 
 

@@ -172,10 +172,11 @@ struct CellOps {
 };
 
 // waves per SIMD the wide tiles are compiled for: the FP64 accumulators of
-// one row block x ten column blocks leave room for three, the FP32 ones for four
-template <typename T, int CBM>
+// one row block x ten column blocks, or the FP32 ones of two, leave room for
+// three; the FP32 ones of one row block for four
+template <typename T, int RBW, int CBM>
 constexpr int cell_waves() {
-  return CBM == 1 ? 1 : (sizeof(T) == 8 ? 3 : 4);
+  return CBM == 1 ? 1 : (sizeof(T) == 8 || RBW > 1 ? 3 : 4);
 }
 
 // Cell GEMM of one colour pass of H^E = T^T Hhat T written per cell in the
@@ -193,7 +194,7 @@ constexpr int cell_waves() {
 // current chunk is multiplied.  T = double (v_mfma_f64_16x16x4) or float
 // (v_mfma_f32_16x16x4, FP32 accumulation).  ENR = false: plain CFE.
 template <typename T, int RBW, int CBM, bool ENR>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(cell_waves<T, CBM>())))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(cell_waves<T, RBW, CBM>())))
 void k_cell3(CellOps<T> a) {
   typedef CellMfma<T> M;
   typedef typename M::acc_t acc_t;
@@ -504,12 +505,24 @@ __global__ __launch_bounds__(256) void k_kb_project(int ncols, const int32_t *__
     const int32_t sl = min(sb + 4 * lane, s1 - 1);
     const int32_t nodes = kbnode[sl];
     const double pv = Pc[sl] * (scale ? scale[nodes] : 1.0);
-    for (int i = 0; i < cnt; ++i) {
-      const int64_t node = __builtin_amdgcn_readlane(nodes, i);
-      const double p = lane_bcast(pv, i);
+    // four entries at a time: their twelve row loads are issued before the
+    // first one is used (the tail repeats the last entry with coefficient 0)
+    for (int i = 0; i < cnt; i += 4) {
+      double xv[4][POST_Q], pj[4];
 #pragma unroll
-      for (int q = 0; q < POST_Q; ++q)
-        acc[q] += p * X[node * ldx + min(c0 + 64 * q + lane, ncols - 1)];
+      for (int j = 0; j < 4; ++j) {
+        const int ii = min(i + j, cnt - 1);
+        const int64_t node = __builtin_amdgcn_readlane(nodes, ii);
+        const double pb = lane_bcast(pv, ii);
+        pj[j] = i + j < cnt ? pb : 0.0;
+#pragma unroll
+        for (int q = 0; q < POST_Q; ++q)
+          xv[j][q] = X[node * ldx + min(c0 + 64 * q + lane, ncols - 1)];
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int q = 0; q < POST_Q; ++q) acc[q] += pj[j] * xv[j][q];
     }
   }
   if (wave > 0)
@@ -671,25 +684,40 @@ __global__ __launch_bounds__(256) void k_expand_init(int64_t n_nodes, int ncols,
 // Y^E[I] = alpha (sum over the cells of atom I of their partial rows + TE[I])
 // + epilogue terms, the partial rows added in cell order (fixed).  One
 // work-group per (atom, 64 columns); the four waves take every fourth function.
-__global__ __launch_bounds__(256) void k_enr_reduce(int nf, int ncols,
+__global__ __launch_bounds__(576) void k_enr_reduce(int nf, int ncols,
                                                     const int32_t *__restrict__ cpair_ptr,
                                                     const int32_t *__restrict__ cpair_cpos,
                                                     const double *__restrict__ Yp, int64_t ldp,
                                                     const double *__restrict__ TE,
                                                     EpiArgs e, double *YE, int64_t ldy) {
   const int I = blockIdx.x;
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int k = threadIdx.x / 64, lane = threadIdx.x % 64;   // one wave per function
   const int col = blockIdx.y * 64 + lane;
-  if (col >= ncols) return;
+  const int colc = min(col, ncols - 1);      // every lane runs: the readlanes below
   const int32_t q0 = cpair_ptr[I], q1 = cpair_ptr[I + 1];
-  for (int k = wave; k < nf; k += 4) {
-    double acc = 0.0;
-    for (int32_t q = q0; q < q1; ++q) acc += Yp[((int64_t)nf * cpair_cpos[q] + k) * ldp + col];
-    const int64_t f = (int64_t)I * nf + k;
-    acc += TE[f * ncols + col];
-    const int64_t o = f * ldy + col;
-    YE[o] = e.alpha * acc + epi_terms(e, o, col);
+  // four partial sums over the atom's pairs (pair q into sum q mod 4), added
+  // in a fixed order; pair positions come 64 at a time by one vector load
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int32_t qb = q0; qb < q1; qb += 64) {
+    const int cnt = min(64, q1 - qb);
+    const int32_t cpv = cpair_cpos[min(qb + lane, q1 - 1)];
+    for (int i = 0; i < cnt; i += 4) {
+      double v[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int64_t cp = __builtin_amdgcn_readlane(cpv, min(i + j, cnt - 1));
+        v[j] = Yp[((int64_t)nf * cp + k) * ldp + colc];
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (i + j < cnt) a[j] += v[j];
+    }
   }
+  if (col >= ncols) return;
+  const int64_t f = (int64_t)I * nf + k;
+  const double acc = (a[0] + a[1]) + (a[2] + a[3]) + TE[f * ncols + col];
+  const int64_t o = f * ldy + col;
+  YE[o] = e.alpha * acc + epi_terms(e, o, col);
 }
 
 // ------------------------------------------------------------------ overlap
@@ -871,7 +899,7 @@ efe_status efe_apply_H_internal(efe_ctx *c, const double *XC, int64_t ldx, const
     launch_cell3<float, 6, 1>(c, c->d_Htile32, c->d_Et32, c->d_Ee32, XC, ldx, scale, XE, lde, Y,
                               ldy, ep.alpha, Yp, ncols, ncols);
   else if (prec == EFE_FP32)
-    launch_cell3<float, 1, 10>(c, c->d_Htile32, c->d_Et32, c->d_Ee32, XC, ldx, scale, XE, lde, Y,
+    launch_cell3<float, 2, 10>(c, c->d_Htile32, c->d_Et32, c->d_Ee32, XC, ldx, scale, XE, lde, Y,
                                ldy, ep.alpha, Yp, ncols, ncols);
   else {
     const int NT = 32;
@@ -905,7 +933,7 @@ efe_status efe_apply_H_internal(efe_ctx *c, const double *XC, int64_t ldx, const
     if (ee.Z1) ee.Z1 += nn * ldy;
     if (ee.Z2) ee.Z2 += nn * ldy;
     if (ee.G) ee.G += nn * ldy;
-    k_enr_reduce<<<dim3(c->natoms, cdiv(ncols, 64)), 256, 0, c->stream>>>(
+    k_enr_reduce<<<dim3(c->natoms, cdiv(ncols, 64)), 64 * nf, 0, c->stream>>>(
         nf, ncols, c->d_cpair_ptr, c->d_cpair_cpos, Yp, ncols, TE, ee, Y + nn * ldy, ldy);
   }
   efe_timer_end(c, EFE_T_POST, t_post);
