@@ -137,3 +137,32 @@ def test_tabulated_enrichment_filter(tabulated):
     tol = filter_tol(m, s.tilde_condition())
     _say("tabulated enrichment filter rel err", err, "tol", tol, "Ritz", lam[:4])
     assert err < tol
+
+
+def test_tabulated_enrichment_scf(tabulated):
+    """Three SCF steps of the 2-atom system enriched from the radial table
+    (efe_scf_step) against the oracle's SCF: energies and Ritz values within
+    1e-8 Ha per step, the bound of the SCF parity tests."""
+    from oracle import enrich, scf
+    from paper_2607_06848_amd import efe
+    w, mesh, s, _, tab = tabulated
+    kT = 500 * 3.166811563e-6
+    es = scf.Electrostatics(mesh, w["xyz"], w["Zs"], w)
+    so = enrich.EFESystem(mesh, w)
+    V0 = wl.random_block(so.rows, w["nvec"], 5)
+    v0 = wl.random_vector(so.rows, 7)
+    ne = float(np.sum(w["Zs"]))
+    hist, _ = scf.scf(so, es, V0, v0, w["nvec"], w["degree"], ne, kT, tol=0.0, max_iter=3,
+                      passes_first=2, passes=1)
+    ctx = efe.Context(w)
+    V = torch.from_numpy(V0).cuda()
+    lam = torch.zeros(w["nvec"], dtype=torch.float64, device="cuda")
+    v0d = torch.from_numpy(v0).cuda()
+    for it in range(3):
+        r = ctx.scf_step(V, lam, v0d, w["degree"], passes_first=2, passes=1, kT=kT)
+        h = hist[it]
+        dl = np.abs(lam.cpu().numpy() - np.asarray(h["lam"])).max()
+        _say("tabulated SCF step", it, "E", r["E"], "dE", r["E"] - h["E"], "dlam", dl)
+        assert abs(r["E"] - h["E"]) < 1e-8
+        assert dl < 1e-8
+    ctx.close()
