@@ -33,6 +33,8 @@ sys.path.insert(0, ROOT)
 
 PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15, "hbm": 8.0e12}
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
+STEP_TIMERS = ("t_filter_ms", "t_rr_ms", "t_poisson_ms", "t_density_ms", "t_operators_ms",
+               "t_bound_ms", "t_energy_ms", "t_other_ms")
 COL_CHUNK = 160   # column chunk of the filter and of one cell GEMM launch
 CELL_KERNEL = {"fp64": "k_cell3<double, 1, 10, true>", "fp32": "k_cell3<float, 2, 10, true>",
                "bf16": "k_cell_bf16<32>"}
@@ -214,7 +216,9 @@ def time_to_scf(args, w, new_run, on_pass):
                                                 f"dE {r['dE']:.2e} drho {r['drho']:.2e} "
                                                 f"passes {r['passes']} max occ res "
                                                 f"{r['max_occ_res']:.2e} "
-                                                f"at {time.perf_counter() - t0:.1f} s"))
+                                                f"at {time.perf_counter() - t0:.1f} s; ms: "
+                                                + " ".join(f"{k[2:-3]} {r[k]:.0f}" for k in
+                                                           STEP_TIMERS)))
         torch.cuda.synchronize()
         t_scf = time.perf_counter() - t0
         ctx.close()

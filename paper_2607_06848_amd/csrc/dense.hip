@@ -685,7 +685,7 @@ efe_status efe_syev_jacobi(efe_ctx *c, int64_t n, const double *H, int64_t ldh, 
   k_round_pairs<<<cdiv((int64_t)(nb - 1) * npair, 256), 256, 0, c->stream>>>(nb, iwork);
   int sw = 0;
   double prev = INFINITY;
-  for (; sw < 40; ++sw) {
+  for (;; ++sw) {
     HIPCHK(c, hipMemsetAsync(off, 0, 2 * 8, c->stream));
     k_offnorm<<<std::min<int64_t>(cdiv(np * np, 256), 1024), 256, 0, c->stream>>>(np, A, np, off);
     HIPCHK(c, hipMemcpyAsync(h2, off, 16, hipMemcpyDeviceToHost, c->stream));
@@ -693,6 +693,7 @@ efe_status efe_syev_jacobi(efe_ctx *c, int64_t n, const double *H, int64_t ldh, 
     if (!std::isfinite(h2[0])) EFE_FAIL(c, EFE_ENUMERIC, "block Jacobi diverged");
     if (!(h2[0] > 1e-28 * hn2)) break;
     if (h2[0] <= 1e-22 * hn2 && h2[0] > 0.25 * prev) break;
+    if (sw == 40) EFE_FAIL(c, EFE_ENOTCONV, "block Jacobi did not converge in 40 sweeps");
     prev = h2[0];
     for (int r = 0; r < nb - 1; ++r) {
       const int *pr = iwork + (int64_t)r * 2 * npair;
@@ -708,7 +709,6 @@ efe_status efe_syev_jacobi(efe_ctx *c, int64_t n, const double *H, int64_t ldh, 
     }
   }
   if (sweeps_out) *sweeps_out = sw;
-  if (sw == 40) EFE_FAIL(c, EFE_ENOTCONV, "block Jacobi did not converge in 40 sweeps");
   // eigenvalues: the diagonal in ascending order; Q[:, i] = V[:n, ord[i]]
   int *ord = iwork + (int64_t)(nb - 1) * 2 * npair;
   k_sort_diag<<<cdiv(np, 256), 256, 0, c->stream>>>(np, A, n, w, ord);

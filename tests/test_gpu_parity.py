@@ -252,3 +252,34 @@ def test_filter_wide_block_chunks():
     tol = filter_tol(m, s.tilde_condition())
     _say("203-column filter rel err", err, "tol", tol)
     assert err < tol
+
+
+@pytest.mark.parametrize("nvec", [1, 65])
+def test_rayleigh_ritz_block_edges(nvec):
+    """Rayleigh-Ritz of 1 vector (the eigensolve's padded blocks all empty but
+    one entry) and 65 (three 32-index blocks padded to four) on the 3-atom
+    p = 6 workload, against the oracle: Ritz values, M-orthonormality and the
+    spanned subspace."""
+    from oracle import eigen
+    from paper_2607_06848_amd import efe
+    w = wl.make("small", nvec=nvec)
+    mesh, s, vq = oracle_system(w)
+    mask = np.zeros(s.rows)
+    mask[s.active()] = 1.0
+    V0 = wl.random_block(s.rows, nvec, 31) * mask[:, None]
+    Vr, lam, res = eigen.rayleigh_ritz(s.apply_H, s.apply_M, V0, mask)
+    ctx = efe.Context(w)
+    ctx.set_potential(torch.from_numpy(np.ascontiguousarray(vq).ravel()).cuda())
+    Vd = dev(V0)
+    lg, rg = ctx.rayleigh_ritz(Vd)
+    lg, rg, Vg = lg.cpu().numpy(), rg.cpu().numpy(), Vd.cpu().numpy()
+    ctx.close()
+    _say("RR edge", nvec, np.abs(lg - lam).max())
+    assert np.abs(lg - lam).max() <= 1e-10 * max(1.0, np.abs(lam).max())
+    S = Vg.T @ s.apply_M(Vg)
+    assert np.abs(S - np.eye(nvec)).max() < 1e-11
+    assert np.abs(rg - res).max() <= 1e-9 * max(1.0, res.max())
+    P = wl.random_block(s.rows, 3, 9) * mask[:, None]
+    pg = Vg @ (Vg.T @ s.apply_M(P))
+    po = Vr @ (Vr.T @ s.apply_M(P))
+    assert np.abs(pg - po).max() < 1e-8 * np.abs(po).max()
