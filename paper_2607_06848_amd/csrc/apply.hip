@@ -20,8 +20,6 @@
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-// columns per lane (x 64) of the row-reduction kernels
-constexpr int POST_Q = 3;
 
 // value of v in lane l (l wave-uniform), for every lane: two readlanes
 __device__ inline double lane_bcast(double v, int l) {
@@ -477,7 +475,12 @@ struct EpiArgs {
 // W[I] += D_I sum_s P^C_s s_node X[node_s] over one work item (atom, support-list
 // range); the items of a node region run back to back, so the rows of X they
 // read are shared through the caches.  Waves take one support node at a time
-// (wave-uniform) for up to 192 columns, three per lane.
+// (wave-uniform); a lane owns two column pairs (256 columns per work-group
+// column block), read as 16-byte pairs with 32-bit offsets (X has an even
+// leading dimension, 16-byte aligned, n_nodes x ld < 2^31: the apply ensures
+// it), and four entries' rows are in flight at a time.
+constexpr int KBP = 2;   // column pairs per lane
+
 __global__ __launch_bounds__(256) void k_kb_project(int ncols, const int32_t *__restrict__ items,
                                                     XcdSplit xs,
                                                     const int32_t *__restrict__ kbnode,
@@ -486,57 +489,69 @@ __global__ __launch_bounds__(256) void k_kb_project(int ncols, const int32_t *__
                                                     const double *__restrict__ scale,
                                                     const double *__restrict__ D,
                                                     double *__restrict__ W) {
-  __shared__ double red[3][64 * POST_Q];
+  __shared__ double2 red[3][64 * KBP];
   const int64_t item = xcd_block(xs);
   if (item < 0) return;
   const int32_t *it = items + 3 * item;
   const int I = it[0];
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
   const int lane = threadIdx.x % 64;
-  const int c0 = blockIdx.y * 64 * POST_Q;
-  double acc[POST_Q] = {0.0, 0.0, 0.0};
+  const int c0 = blockIdx.y * 128 * KBP;
+  const int npv = (min(ncols - c0, 128 * KBP) + 1) / 2;   // column pairs of this block
+  int pofs[KBP];
+#pragma unroll
+  for (int q = 0; q < KBP; ++q) pofs[q] = c0 + 2 * min(lane + 64 * q, npv - 1);
+  double2 acc[KBP];
+#pragma unroll
+  for (int q = 0; q < KBP; ++q) acc[q] = make_double2(0.0, 0.0);
   // entries it[1] + wave + 4 i: node numbers and coefficients (times the row
   // scale) come in 64 at a time by vector loads and reach the wave by
-  // readlane; clamped columns keep the row loads unconditional (their sums
-  // are not stored)
+  // readlane; clamped pairs keep the row loads unconditional (their sums are
+  // not stored)
   const int32_t s0 = it[1], s1 = it[2];
+  const uint32_t ld = (uint32_t)ldx;
   for (int32_t sb = s0 + wave; sb < s1; sb += 256) {
     const int cnt = min(64, (s1 - sb + 3) / 4);
     const int32_t sl = min(sb + 4 * lane, s1 - 1);
     const int32_t nodes = kbnode[sl];
     const double pv = Pc[sl] * (scale ? scale[nodes] : 1.0);
-    // four entries at a time: their twelve row loads are issued before the
-    // first one is used (the tail repeats the last entry with coefficient 0)
     for (int i = 0; i < cnt; i += 4) {
-      double xv[4][POST_Q], pj[4];
+      double2 xv[4][KBP];
+      double pj[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int ii = min(i + j, cnt - 1);
-        const int64_t node = __builtin_amdgcn_readlane(nodes, ii);
+        const uint32_t node = (uint32_t)__builtin_amdgcn_readlane(nodes, ii);
         const double pb = lane_bcast(pv, ii);
         pj[j] = i + j < cnt ? pb : 0.0;
 #pragma unroll
-        for (int q = 0; q < POST_Q; ++q)
-          xv[j][q] = X[node * ldx + min(c0 + 64 * q + lane, ncols - 1)];
+        for (int q = 0; q < KBP; ++q)
+          xv[j][q] = *reinterpret_cast<const double2 *>(X + (node * ld + (uint32_t)pofs[q]));
       }
 #pragma unroll
       for (int j = 0; j < 4; ++j)
 #pragma unroll
-        for (int q = 0; q < POST_Q; ++q) acc[q] += pj[j] * xv[j][q];
+        for (int q = 0; q < KBP; ++q) {
+          acc[q].x += pj[j] * xv[j][q].x;
+          acc[q].y += pj[j] * xv[j][q].y;
+        }
     }
   }
   if (wave > 0)
 #pragma unroll
-    for (int q = 0; q < POST_Q; ++q) red[wave - 1][64 * q + lane] = acc[q];
+    for (int q = 0; q < KBP; ++q) red[wave - 1][64 * q + lane] = acc[q];
   __syncthreads();
   if (wave == 0)
 #pragma unroll
-    for (int q = 0; q < POST_Q; ++q) {
-      const int col = c0 + 64 * q + lane;
-      if (col < ncols)
-        atomicAdd(&W[(int64_t)I * ncols + col],
-                  D[I] * (acc[q] + red[0][64 * q + lane] + red[1][64 * q + lane] +
-                          red[2][64 * q + lane]));
+    for (int q = 0; q < KBP; ++q) {
+      const int pp = lane + 64 * q;
+      if (pp >= npv) continue;
+      const int col = c0 + 2 * pp;
+      const double2 r0 = red[0][64 * q + lane], r1 = red[1][64 * q + lane],
+                    r2 = red[2][64 * q + lane];
+      atomicAdd(&W[(int64_t)I * ncols + col], D[I] * (acc[q].x + r0.x + r1.x + r2.x));
+      if (col + 1 < ncols)
+        atomicAdd(&W[(int64_t)I * ncols + col + 1], D[I] * (acc[q].y + r0.y + r1.y + r2.y));
     }
 }
 
@@ -608,6 +623,8 @@ __device__ inline double epi_terms(const EpiArgs &e, int64_t o, int col) {
 // in coalesced 16-byte pieces, and the threads of a wave share one or two
 // nodes, whose projector entries they loop over together.  Even ld (the host
 // checks it) keeps the pairs aligned.
+constexpr int EXP_P = 2;   // column pairs per thread of k_expand_init
+
 __global__ __launch_bounds__(256) void k_expand_init(int64_t n_nodes, int ncols,
                                                      const int32_t *__restrict__ kbnm_ptr,
                                                      const int32_t *__restrict__ kbnm_atom,
@@ -616,68 +633,91 @@ __global__ __launch_bounds__(256) void k_expand_init(int64_t n_nodes, int ncols,
                                                      const double *__restrict__ minv,
                                                      EpiArgs e, double *Y, int64_t ldy,
                                                      bool vec) {
-  const int npr = (ncols + 1) / 2;
+  const int npr = (ncols + 1) / 2;             // column pairs of a node
+  const int nth = (npr + EXP_P - 1) / EXP_P;   // threads of a node
   const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (idx >= n_nodes * npr) return;
+  if (idx >= n_nodes * nth) return;
   int64_t node;
-  int c0;
-  if (n_nodes * npr < (1ll << 31)) {          // 32-bit division where it fits
-    node = (uint32_t)idx / (uint32_t)npr;
-    c0 = 2 * (int)((uint32_t)idx - (uint32_t)node * (uint32_t)npr);
+  int j;
+  if (n_nodes * nth < (1ll << 31)) {          // 32-bit division where it fits
+    node = (uint32_t)idx / (uint32_t)nth;
+    j = (int)((uint32_t)idx - (uint32_t)node * (uint32_t)nth);
   } else {
-    node = idx / npr;
-    c0 = 2 * (int)(idx % npr);
+    node = idx / nth;
+    j = (int)(idx % nth);
   }
-  const bool two = c0 + 1 < ncols;
-  const int64_t o = node * ldy + c0;
+  // this thread's pairs: j, j + nth, ... (adjacent threads, adjacent pairs)
+  int c0[EXP_P];
+  bool has[EXP_P], two[EXP_P];
+#pragma unroll
+  for (int q = 0; q < EXP_P; ++q) {
+    c0[q] = 2 * (j + q * nth);
+    has[q] = c0[q] < ncols;
+    two[q] = c0[q] + 1 < ncols;
+  }
+  const int64_t rowo = node * ldy;
   // pairs by 16-byte accesses when the layout allows it (vec: even ld,
   // aligned arrays), else element by element
-  auto ld2 = [&](const double *p) -> double2 {
-    if (vec && two) return *reinterpret_cast<const double2 *>(p + o);
+  auto ld2 = [&](const double *p, int q) -> double2 {
+    const int64_t o = rowo + c0[q];
+    if (vec && two[q]) return *reinterpret_cast<const double2 *>(p + o);
     double2 r;
-    r.x = p[o];
-    r.y = two ? p[o + 1] : 0.0;
+    r.x = has[q] ? p[o] : 0.0;
+    r.y = two[q] ? p[o + 1] : 0.0;
     return r;
   };
   // the streamed rows first, so that they are in flight while the
   // projector entries (two dependent loads each) come in
-  double2 z1 = make_double2(0.0, 0.0), z2 = z1, g = z1;
-  double cl0 = 0.0, cl1 = 0.0;
-  if (e.Z1) z1 = ld2(e.Z1);
-  if (e.Z2) z2 = ld2(e.Z2);
-  if (e.G) {
-    g = ld2(e.G);
-    cl0 = e.Cl[c0];
-    cl1 = two ? e.Cl[c0 + 1] : 0.0;
+  double2 z1[EXP_P], z2[EXP_P], g[EXP_P], cl[EXP_P];
+#pragma unroll
+  for (int q = 0; q < EXP_P; ++q) {
+    z1[q] = z2[q] = g[q] = cl[q] = make_double2(0.0, 0.0);
+    if (e.Z1) z1[q] = ld2(e.Z1, q);
+    if (e.Z2) z2[q] = ld2(e.Z2, q);
+    if (e.G) {
+      g[q] = ld2(e.G, q);
+      cl[q].x = has[q] ? e.Cl[c0[q]] : 0.0;
+      cl[q].y = two[q] ? e.Cl[c0[q] + 1] : 0.0;
+    }
   }
   const bool inner = minv[node] != 0.0;
-  double a0 = 0.0, a1 = 0.0;
+  double2 a[EXP_P];
+#pragma unroll
+  for (int q = 0; q < EXP_P; ++q) a[q] = make_double2(0.0, 0.0);
   if (kbnm_ptr) {
     const int32_t e0 = kbnm_ptr[node], e1 = kbnm_ptr[node + 1];
     for (int32_t en = e0; en < e1; ++en) {
       const double p = Pc_nm[en];
-      const double *w = W + (int64_t)kbnm_atom[en] * ncols + c0;
-      a0 += p * w[0];
-      if (two) a1 += p * w[1];
+      const double *w = W + (int64_t)kbnm_atom[en] * ncols;
+#pragma unroll
+      for (int q = 0; q < EXP_P; ++q) {
+        if (has[q]) a[q].x += p * w[c0[q]];
+        if (two[q]) a[q].y += p * w[c0[q] + 1];
+      }
     }
   }
-  double2 v;
-  v.x = e.alpha * (a0 + g.x * cl0);
-  v.y = e.alpha * (a1 + g.y * cl1);
-  if (e.Z1) {
-    v.x += e.beta * z1.x;
-    v.y += e.beta * z1.y;
-  }
-  if (e.Z2) {
-    v.x += e.gamma * z2.x;
-    v.y += e.gamma * z2.y;
-  }
-  if (!inner) v.x = v.y = 0.0;
-  if (vec && two) {
-    *reinterpret_cast<double2 *>(Y + o) = v;
-  } else {
-    Y[o] = v.x;
-    if (two) Y[o + 1] = v.y;
+#pragma unroll
+  for (int q = 0; q < EXP_P; ++q) {
+    if (!has[q]) continue;
+    double2 v;
+    v.x = e.alpha * (a[q].x + g[q].x * cl[q].x);
+    v.y = e.alpha * (a[q].y + g[q].y * cl[q].y);
+    if (e.Z1) {
+      v.x += e.beta * z1[q].x;
+      v.y += e.beta * z1[q].y;
+    }
+    if (e.Z2) {
+      v.x += e.gamma * z2[q].x;
+      v.y += e.gamma * z2[q].y;
+    }
+    if (!inner) v.x = v.y = 0.0;
+    const int64_t o = rowo + c0[q];
+    if (vec && two[q]) {
+      *reinterpret_cast<double2 *>(Y + o) = v;
+    } else {
+      Y[o] = v.x;
+      if (two[q]) Y[o + 1] = v.y;
+    }
   }
 }
 
@@ -875,13 +915,13 @@ efe_status efe_apply_H_internal(efe_ctx *c, const double *XC, int64_t ldx, const
           k_kb_project1<<<c->n_kb_items, 256, 0, c->stream>>>(c->d_kb_items, c->d_kbnode,
                                                               c->d_Pc_am, XC, ldx, scale, c->d_D, W);
         else
-          k_kb_project<<<dim3(8 * xs.max_len(), cdiv(ncols, 64 * POST_Q)), 256, 0, c->stream>>>(
+          k_kb_project<<<dim3(8 * xs.max_len(), cdiv(ncols, 128 * KBP)), 256, 0, c->stream>>>(
               ncols, c->d_kb_items, xs, c->d_kbnode, c->d_Pc_am, XC, ldx, scale, c->d_D, W);
       }
     }
     auto al = [](const double *p) { return p == nullptr || (uintptr_t)p % 16 == 0; };
     const bool vec = ldy % 2 == 0 && al(Y) && al(ep.Z1) && al(ep.Z2) && al(ep.G);
-    k_expand_init<<<cdiv(nn * ((ncols + 1) / 2), 256), 256, 0, c->stream>>>(
+    k_expand_init<<<cdiv(nn * (((ncols + 1) / 2 + EXP_P - 1) / EXP_P), 256), 256, 0, c->stream>>>(
         nn, ncols, c->nproj ? c->d_kbnm_ptr : nullptr, c->d_kbnm_atom, c->d_Pc_nm, W, c->d_minv,
         ec, Y, ldy, vec);
     efe_timer_end(c, EFE_T_PRE, t);
