@@ -211,6 +211,7 @@ def time_to_scf(args, w, new_run, on_pass):
                            max_iter=args.max_scf_steps,
                            prec=prec_k, passes_first=args.passes_first, passes=1,
                            tau=args.tau, max_passes=args.max_passes, kerker_k0=args.kerker,
+                           mix_beta=args.mix_beta, mix_history=args.mix_history,
                            progress=on_pass,
                            log=lambda i, r: log(f" {name} step {i}: E {r['E']:.8f} "
                                                 f"dE {r['dE']:.2e} drho {r['drho']:.2e} "
@@ -233,7 +234,8 @@ def time_to_scf(args, w, new_run, on_pass):
                      "filter_precision": "fp64" if prec_k == 0 else "fp32",
                      "max_occ_res": [h["max_occ_res"] for h in hist],
                      "E_per_step": [h["E"] for h in hist],
-                     "tau": args.tau, "kerker_k0": args.kerker, "scf_tol": args.scf_tol}
+                     "tau": args.tau, "kerker_k0": args.kerker, "scf_tol": args.scf_tol,
+                     "mix_beta": args.mix_beta, "mix_history": args.mix_history}
         log(f"SCF {name}: {len(hist)} steps, {t_scf:.1f} s, E {hist[-1]['E']:.8f}")
     for other in ("fp32_learned", "fp64_learned", "fp32_sad"):
         if other in res and "fp64_sad" in res:
@@ -272,6 +274,10 @@ def main():
                     help="time-to-SCF runs: minimum passes of the first SCF step")
     ap.add_argument("--kerker", type=float, default=0.0,
                     help="time-to-SCF runs: Kerker k0 of the mixing (0: plain Anderson)")
+    ap.add_argument("--mix-beta", type=float, default=0.3,
+                    help="time-to-SCF runs: Anderson mixing parameter")
+    ap.add_argument("--mix-history", type=int, default=8,
+                    help="time-to-SCF runs: Anderson history depth")
     ap.add_argument("--scf-tol", type=float, default=1e-5,
                     help="time-to-SCF runs: stop when |dE| per atom and the density change "
                          "per electron are both below this")
