@@ -39,6 +39,11 @@ Readings (the paper gives no discretization or SCF details):
     0 at r = 0); the 3-D enrichment function is S_lm(x) f_l(r) h(r) with
     the solid harmonics of the Gaussian enrichment, f_l by cubic Hermite
     interpolation of the table.
+  * Atomic fields (Sec. III.C, one species): rho^(I) = the atom's output
+    density and phi^(I) the potential of rho^(I) + b^(I) (b the Gaussian
+    smeared charge), tabulated like f_l; the pair energies <n_I, n_J> by
+    radial-angular quadrature (trapezoid over the table points, 64-point
+    Gauss-Legendre in the angle), zero beyond the tables.
 """
 import numpy as np
 from scipy.linalg import eigh_tridiagonal, solve_banded
@@ -258,3 +263,47 @@ def enrichment_tabulated(mesh, center, cells, lmax, table):
     phi = S * rad
     grad = dS * rad[..., None] + (S * drad)[..., None] * d[..., None, :]
     return phi, grad
+
+
+# ---------------------------------------------------------------- atomic fields
+def atomic_tables(atom, p):
+    """The isolated atom's density rho^(I) and the potential phi^(I) of
+    rho^(I) + b^(I) (the neutral atom: b the Gaussian smeared nuclear charge
+    of width r_b = loc_rc), Sec. III.C, tabulated at r = i h (i = 0..n) with
+    slopes, in the form of radial_table: rho from the last output density;
+    phi = v_H[rho] - Z erf(r / r_b) / r with v_H by the three-point rule
+    (hartree); both even in r, so their r = 0 values come from
+    (4 f(h) - f(2h)) / 3.  Returns dict(rho=(f, df), phi=(f, df), dr)."""
+    r, h = atom["r"], atom["h"]
+    rho = atom["rho"]
+    phi = hartree(rho, r, h) - float(p["Z"]) * psp.erf_over_r(r, p["loc_rc"])
+
+    def tab(v):
+        f = np.empty(len(r) + 1)
+        f[1:] = v
+        f[0] = (4.0 * f[1] - f[2]) / 3.0
+        df = np.empty_like(f)
+        df[1:-1] = (f[2:] - f[:-2]) / (2.0 * h)
+        df[0] = 0.0
+        df[-1] = (f[-1] - f[-2]) / h
+        return f, df
+    return dict(rho=tab(rho), phi=tab(phi), dr=h)
+
+
+def pair_coulomb(tabI, tabJ, Z, rb, R, nmu=64):
+    """<n_I, n_J> = int n_I(x) phi_J(|x - R|) d^3x for spherical n_I = rho_I +
+    b_I (b the Gaussian smeared charge -Z) and phi_J the potential of n_J:
+    2 pi sum_i w_i r_i^2 n_I(r_i) sum_k w_k phi_J(d_ik), d_ik^2 = r_i^2 + R^2 -
+    2 r_i R mu_k, over the table points r_i (trapezoid weights) and nmu
+    Gauss-Legendre nodes mu_k; phi_J by cubic Hermite interpolation, zero
+    beyond its table.  R = 0 gives the self term 4 pi int n phi r^2 dr."""
+    dr = tabI["dr"]
+    f = tabI["rho"][0]
+    ri = dr * np.arange(len(f))
+    wi = np.full(len(f), dr)
+    wi[0] = wi[-1] = 0.5 * dr
+    n_i = f + psp.b_smear(ri, Z, rb)
+    mu, wm = np.polynomial.legendre.leggauss(nmu)
+    d = np.sqrt(np.maximum(ri[:, None] ** 2 + R * R - 2.0 * ri[:, None] * R * mu[None, :], 0.0))
+    phij, _ = hermite(tabJ["phi"][0], tabJ["phi"][1], tabJ["dr"], d)
+    return float(2.0 * np.pi * np.sum(wi * ri * ri * n_i * (phij @ wm)))

@@ -152,10 +152,19 @@ class Electrostatics:
         self.phi_at = np.zeros(X.shape[:2])
         self.v_short = np.zeros(X.shape[:2])
         a, rb = prm["rho_alpha"], prm["loc_rc"]
+        # atomic densities and potentials: Gaussian forms, or (atom_table, one
+        # species) the isolated atom's radial solution (radial.atomic_tables)
+        self.tab = prm.get("atom_table")
+        if self.tab is not None:
+            from . import radial
         for R, Z in zip(self.xyz, self.Z):
             r = np.linalg.norm(X - R, axis=-1)
-            self.rho_at += psp.rho_atom(r, Z, a)
-            self.phi_at += psp.phi_atom(r, Z, a, rb)
+            if self.tab is None:
+                self.rho_at += psp.rho_atom(r, Z, a)
+                self.phi_at += psp.phi_atom(r, Z, a, rb)
+            else:
+                self.rho_at += radial.hermite(*self.tab["rho"], self.tab["dr"], r)[0]
+                self.phi_at += radial.hermite(*self.tab["phi"], self.tab["dr"], r)[0]
             self.v_short += psp.v_short(r, prm["loc_amp"], prm["loc_rg"])
         K = mesh.stiffness_cell()
         d = np.zeros(mesh.n_nodes)
@@ -205,7 +214,17 @@ class Electrostatics:
 
     def pair_energy(self):
         """1/2 sum_IJ <n_I, n_J> with n_I = rho^(I) + b^(I), in closed form from
-        Gaussian-Gaussian Coulomb integrals (the I = J terms included)."""
+        Gaussian-Gaussian Coulomb integrals (the I = J terms included); with
+        tabulated atoms by radial.pair_coulomb."""
+        if self.tab is not None:
+            from . import radial
+            rb = self.prm["loc_rc"]
+            e = 0.0
+            for i in range(len(self.Z)):
+                for j in range(len(self.Z)):
+                    R = float(np.linalg.norm(self.xyz[i] - self.xyz[j]))
+                    e += 0.5 * radial.pair_coulomb(self.tab, self.tab, self.Z[i], rb, R)
+            return e
         a = self.prm["rho_alpha"]
         ab = 1.0 / self.prm["loc_rc"] ** 2
         e = 0.0

@@ -171,3 +171,66 @@ def test_enrichment_tables_of_the_synthetic_atom(atom):
             assert abs(np.gradient(R, h)[i]) < 5e-3
             assert 1 - radial.truncated_norm(u, r, h, r0) <= 5e-3
         assert tab["rc"][l] == pytest.approx(r0 * (1 + 1 / 0.33))
+
+
+def _gaussian_atom_tables(h=0.04, n=1000):
+    """Tables of the Gaussian atomic density and its neutral potential with
+    exact slopes (psp's closed forms), in the layout of atomic_tables."""
+    from scipy.special import erf
+    p = wl.PSP
+    Z, a, rb = p["Z"], p["rho_alpha"], p["loc_rc"]
+    x = h * np.arange(n + 1)
+    rho = psp.rho_atom(x, Z, a)
+    phi = psp.phi_atom(x, Z, a, rb)
+    xs = np.where(x > 0, x, 1.0)
+
+    def g(s):   # d/dr erf(s r) / r, r > 0
+        return (2 / np.sqrt(np.pi)) * s * np.exp(-(s * xs) ** 2) / xs - erf(s * xs) / xs ** 2
+    dphi = np.where(x > 0, Z * (g(np.sqrt(a)) - g(1 / rb)), 0.0)
+    return dict(rho=(rho, -2 * a * x * rho), phi=(phi, dphi), dr=h)
+
+
+def test_pair_coulomb_reproduces_gaussian_closed_forms():
+    """<n_I, n_J> by the radial-angular quadrature of pair_coulomb against the
+    Gaussian-Gaussian Coulomb closed forms (self term and three separations)."""
+    p = wl.PSP
+    Z, a, rb = p["Z"], p["rho_alpha"], p["loc_rc"]
+    tab = _gaussian_atom_tables()
+    ab = 1 / rb ** 2
+    for R in (0.0, 1.5, 3.0, 6.0):
+        ex = Z * Z * (psp.gauss_coulomb(R, a, a) - 2 * psp.gauss_coulomb(R, a, ab)
+                      + psp.gauss_coulomb(R, ab, ab))
+        assert abs(radial.pair_coulomb(tab, tab, Z, rb, R) - float(ex)) < 1e-9
+
+
+def test_tabulated_electrostatics_match_the_gaussian_forms():
+    """Electrostatics with Gaussian atom tables gives the analytic atomic
+    density, potential and geometry energy of the Gaussian atoms, to the
+    cubic Hermite error h^4 max|f^(4)| / 384 (about 1.2e-7 of rho(0) for the
+    density at h = 0.04)."""
+    from oracle import scf
+    w = wl.make("eig2")
+    mesh = fe.Mesh(w["lo"], w["hi"], w["ncell"], w["p"], w["nq"])
+    es0 = scf.Electrostatics(mesh, w["xyz"], w["Zs"], w)
+    es1 = scf.Electrostatics(mesh, w["xyz"], w["Zs"], dict(w, atom_table=_gaussian_atom_tables()))
+    assert np.abs(es1.rho_at - es0.rho_at).max() < 2e-7 * np.abs(es0.rho_at).max()
+    assert np.abs(es1.phi_at - es0.phi_at).max() < 2e-7 * np.abs(es0.phi_at).max()
+    assert abs(es1.constant_energy() - es0.constant_energy()) < 1e-8
+
+
+def test_atomic_tables_of_the_synthetic_atom(atom):
+    """The density table integrates to Z; w = r (phi + Z erf(r/r_b)/r) solves
+    the three-point Poisson equation w'' = -4 pi r rho at every interior
+    point; the neutral atom's potential vanishes at the end of the table."""
+    p = wl.PSP
+    tab = radial.atomic_tables(atom, p)
+    h = tab["dr"]
+    x = h * np.arange(len(tab["rho"][0]))
+    wq = np.full(len(x), h)
+    wq[0] = wq[-1] = h / 2
+    assert abs(4 * np.pi * np.sum(wq * x * x * tab["rho"][0]) - p["Z"]) < 1e-9
+    r = x[1:]
+    wv = r * tab["phi"][0][1:] + p["Z"] * r * psp.erf_over_r(r, p["loc_rc"])
+    res = (wv[2:] - 2 * wv[1:-1] + wv[:-2]) / h ** 2 + 4 * np.pi * r[1:-1] * tab["rho"][0][2:-1]
+    assert np.abs(res).max() < 1e-9 * np.abs(4 * np.pi * r * tab["rho"][0][1:]).max()
+    assert abs(tab["phi"][0][-1]) < 1e-9
