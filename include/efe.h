@@ -79,7 +79,17 @@ typedef struct {
  *                (l <= enr_lmax), cubic Hermite interpolation, zero beyond
  *                the table; h ends at enr_tab_rc[l] with smoothness enr_t;
  *                enr_rcut (the support radius) must cover every enr_tab_rc[l]
- * xyz, Z and enr_tab are host arrays read during efe_setup_mesh only. */
+ *   atom_tab_n   > 0: atomic densities and potentials (Sec. III.C) from the
+ *                isolated atom's radial solution instead of the Gaussian
+ *                forms (rho_alpha unused): rows of atom_tab, each of
+ *                atom_tab_n values at r = i atom_tab_dr: rho^(I), its slope,
+ *                phi^(I) (the potential of rho^(I) + the Gaussian smeared
+ *                charge of width loc_rc), its slope (efe_radial_atom); cubic
+ *                Hermite interpolation, zero beyond the table; one species
+ *                (every Z equal); the pair energies <n_I, n_J> by
+ *                radial-angular quadrature over the table points
+ * xyz, Z, enr_tab and atom_tab are host arrays read during efe_setup_mesh
+ * only. */
 typedef struct {
   int32_t natoms;
   const double *xyz;
@@ -93,6 +103,9 @@ typedef struct {
   double enr_tab_dr;
   const double *enr_tab;
   double enr_tab_rc[3];
+  int32_t atom_tab_n;
+  double atom_tab_dr;
+  const double *atom_tab;
 } efe_system_desc;
 
 /* Build the mesh tables, the enrichment and projector data and the overlap
@@ -120,7 +133,12 @@ efe_status efe_setup_mesh(const efe_mesh_desc *mesh, const efe_system_desc *sys,
  *   u[(l nstates + k) n + i] (h sum u^2 = 1, largest |u| positive),
  *   rho[n] (the last output density), r0[lmax+1],
  *   tab[2(lmax+1)][n+1]: rows 2l, 2l+1 = f_l, f_l' at r = i h (i = 0..n),
- *   the layout of efe_system_desc.enr_tab (cutoff radius r0 (1 + 1/t)).
+ *   the layout of efe_system_desc.enr_tab (cutoff radius r0 (1 + 1/t)),
+ *   atab[4][n+1] (may be NULL): rho of the last output density, its slope,
+ *   the potential of rho + the Gaussian smeared charge (width loc_rc) with
+ *   v_H by the same three-point rule, its slope, at r = i h (values at 0
+ *   from (4 f(h) - f(2h))/3, slopes by central differences), the layout of
+ *   efe_system_desc.atom_tab.
  * Allocates and frees its own device workspace; reads sys on the host.
  * EFE_ENOTCONV when maxit iterations do not reach tol (outputs are those of
  * the last iteration); messages through efe_last_error(NULL). */
@@ -141,7 +159,7 @@ typedef struct {
 
 efe_status efe_radial_atom(const efe_system_desc *sys, int32_t atom,
                            const efe_radial_params *prm, void *stream, double *eps, double *u,
-                           double *occ, double *rho, double *r0, double *tab,
+                           double *occ, double *rho, double *r0, double *tab, double *atab,
                            efe_radial_report *rep);
 
 /* sizes[0..7] = rows, n_nodes, n_dof (interior nodes + enrichment), n_enr,

@@ -263,6 +263,11 @@ extern "C" efe_status efe_setup_mesh(const efe_mesh_desc *mesh, const efe_system
   const bool tab = sys->enr_lmax >= 0 && sys->enr_tab_n > 0;
   if (sys->enr_lmax >= 0 && !(sys->enr_rcut > 0 && sys->enr_t > 0 && (tab || sys->enr_alpha > 0)))
     return EFE_EINVAL;
+  if (sys->atom_tab_n > 0) {
+    if (!sys->atom_tab || sys->atom_tab_n < 2 || !(sys->atom_tab_dr > 0)) return EFE_EINVAL;
+    for (int I = 1; I < sys->natoms; ++I)
+      if (sys->Z[I] != sys->Z[0]) return EFE_EINVAL;   // one species
+  }
   if (tab) {
     if (!sys->enr_tab || sys->enr_tab_n < 2 || !(sys->enr_tab_dr > 0)) return EFE_EINVAL;
     for (int l = 0; l <= sys->enr_lmax; ++l)
@@ -316,6 +321,11 @@ extern "C" efe_status efe_setup_mesh(const efe_mesh_desc *mesh, const efe_system
     for (int l = 0; l <= sys->enr_lmax; ++l) c->tab_rc[l] = sys->enr_tab_rc[l];
     c->tab_host.assign(sys->enr_tab, sys->enr_tab + (size_t)2 * (sys->enr_lmax + 1) * c->ntab);
   }
+  if (sys->atom_tab_n > 0) {
+    c->natab = sys->atom_tab_n;
+    c->atab_dr = sys->atom_tab_dr;
+    c->atab_host.assign(sys->atom_tab, sys->atom_tab + (size_t)4 * c->natab);
+  }
   c->nf = c->lmax < 0 ? 0 : (c->lmax + 1) * (c->lmax + 1);
   if (c->natoms == 0) c->nf = 0;
   c->n_enr = (int64_t)c->natoms * c->nf;
@@ -340,6 +350,7 @@ extern "C" efe_status efe_setup_mesh(const efe_mesh_desc *mesh, const efe_system
     TRY(upload(c, &c->d_xyz, xyz));
     TRY(upload(c, &c->d_Zs, Zs));
     if (c->ntab > 0) TRY(upload(c, &c->d_enr_tab, c->tab_host));
+    if (c->natab > 0) TRY(upload(c, &c->d_atom_tab, c->atab_host));
     TRY(efe_build_reference(c));
 
     SupportTables E, K;

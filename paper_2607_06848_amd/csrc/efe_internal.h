@@ -48,6 +48,11 @@ struct efe_ctx {
   double tab_dr = 0.0, tab_rc[3] = {0.0, 0.0, 0.0};
   double *d_enr_tab = nullptr;
   std::vector<double> tab_host;
+  // tabulated atomic density and potential (natab = 0: Gaussian forms)
+  int natab = 0;
+  double atab_dr = 0.0;
+  double *d_atom_tab = nullptr;
+  std::vector<double> atab_host;
 
   // support tables (host copies kept for efe_get_support)
   std::vector<int32_t> enr_ptr, enr_cells, kb_ptr, kb_cells;

@@ -12,7 +12,10 @@
 // neg(A + D q q^T) = neg(A) - 1 + [q^T A^-1 q > -1/D], q^T A^-1 q from the
 // same LDL^T sweep.  Vectors by inverse iteration (the s channel with the
 // projector: (T - mu)^-1 q).  Hartree by the same three-point rule, PW92,
-// Fermi occupations of the 2(2l+1)-fold levels, linear density mixing.
+// Fermi occupations of the 2(2l+1)-fold levels, linear density mixing.  The
+// converged density and the potential of the neutral atom (density plus the
+// Gaussian smeared nuclear charge) are tabulated for the atomic fields of
+// Sec. III.C.
 #include <cmath>
 
 #include "efe_device.h"
@@ -395,12 +398,65 @@ __global__ __launch_bounds__(256) void k_rad_tables(RadArgs a, const double *__r
   if (t == 0) r0_out[l] = best[0] == INT32_MAX ? r0_max : rgrid(a, best[0]);
 }
 
+// atomic fields of the converged atom: rows rho, rho', phi, phi' at r = i h
+// (i = 0..n), phi = v_H[rho] - Z erf(r/rb)/r with v_H by the same Thomas
+// solve as k_rad_veff; values at r = 0 from (4 f(h) - f(2h))/3, slopes by
+// central differences (one-sided at the end, 0 at r = 0); one thread
+__global__ void k_rad_atab(RadArgs a, double Z, double rb, const double *__restrict__ rho,
+                           double *__restrict__ cp, double *__restrict__ dp,
+                           double *__restrict__ atab) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int n = a.n, m = n + 1;
+  const double h = a.h;
+  double Q = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const double r = rgrid(a, i);
+    Q += r * r * rho[i];
+  }
+  Q *= 4.0 * M_PI * h;
+  for (int i = 0; i < n; ++i) {
+    const double r = rgrid(a, i);
+    double g = -4.0 * M_PI * h * h * r * rho[i];
+    if (i == n - 1) g -= Q;
+    if (i == 0) {
+      cp[0] = 1.0 / -2.0;
+      dp[0] = g / -2.0;
+    } else {
+      const double den = -2.0 - cp[i - 1];
+      cp[i] = 1.0 / den;
+      dp[i] = (g - dp[i - 1]) / den;
+    }
+  }
+  double *fr = atab, *dfr = atab + m, *fp = atab + 2 * m, *dfp = atab + 3 * m;
+  double w = dp[n - 1];
+  for (int i = n - 1; i >= 0; --i) {
+    if (i < n - 1) w = dp[i] - cp[i] * w;
+    const double r = rgrid(a, i), x = r / rb;
+    const double eor = x < 1e-6 ? (2.0 / (rb * sqrt(M_PI))) * (1.0 - x * x / 3.0) : erf(x) / r;
+    fp[i + 1] = w / r - Z * eor;
+    fr[i + 1] = rho[i];
+  }
+  fr[0] = (4.0 * fr[1] - fr[2]) / 3.0;
+  fp[0] = (4.0 * fp[1] - fp[2]) / 3.0;
+  for (int i = 0; i <= n; ++i) {
+    if (i == 0) {
+      dfr[0] = dfp[0] = 0.0;
+    } else if (i == n) {
+      dfr[n] = (fr[n] - fr[n - 1]) / h;
+      dfp[n] = (fp[n] - fp[n - 1]) / h;
+    } else {
+      dfr[i] = (fr[i + 1] - fr[i - 1]) / (2.0 * h);
+      dfp[i] = (fp[i + 1] - fp[i - 1]) / (2.0 * h);
+    }
+  }
+}
+
 }  // namespace
 
 extern "C" efe_status efe_radial_atom(const efe_system_desc *sys, int32_t atom,
                                       const efe_radial_params *prm, void *stream, double *eps,
                                       double *u, double *occ, double *rho, double *r0,
-                                      double *tab, efe_radial_report *rep) {
+                                      double *tab, double *atab, efe_radial_report *rep) {
   auto fail = [](efe_status st, const std::string &m) {
     efe_set_global_error("efe_radial_atom: " + m);
     return st;
@@ -458,6 +514,7 @@ extern "C" efe_status efe_radial_atom(const efe_system_desc *sys, int32_t atom,
   if (!out && it > prm->maxit) it = prm->maxit;
   if (!out) {
     k_rad_tables<<<a.lmax + 1, 256, 0, st>>>(a, u, sys->enr_t, 10.0, 5e-3, 5e-3, tab, r0);
+    if (atab) k_rad_atab<<<1, 64, 0, st>>>(a, Z, sys->loc_rc, rho, cp, dp, atab);
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
       out = fail(EFE_EHIP, "HIP error in the radial tables");
   }

@@ -64,10 +64,13 @@ __device__ inline double erf_over_r(double r, double a) {
   return x < 1e-6 ? (2.0 / (a * sqrt(M_PI))) * (1.0 - x * x / 3.0) : erf(x) / r;
 }
 
-// rho^(I), phi^(I) and v_short summed over atoms at every Gauss point
+// rho^(I), phi^(I) and v_short summed over atoms at every Gauss point:
+// Gaussian forms, or (atab != nullptr) the tabulated radial solution (rows
+// rho, rho', phi, phi' of natab points at r = i adr)
 __global__ void k_atomic_fields(MeshGeo g, const double *__restrict__ xq1, int natoms,
                                 const double *__restrict__ xyz, const double *__restrict__ Z,
                                 double a_rho, double rb, double amp, double rg,
+                                const double *__restrict__ atab, int natab, double adr,
                                 double *__restrict__ rho_at, double *__restrict__ phi_at,
                                 double *__restrict__ v_short) {
   const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -80,13 +83,107 @@ __global__ void k_atomic_fields(MeshGeo g, const double *__restrict__ xq1, int n
   for (int I = 0; I < natoms; ++I) {
     const double dx = x[0] - xyz[3 * I], dy = x[1] - xyz[3 * I + 1], dz = x[2] - xyz[3 * I + 2];
     const double r2 = dx * dx + dy * dy + dz * dz, r = sqrt(r2);
-    ra += Z[I] * norm * exp(-a_rho * r2);
-    pa += Z[I] * (erf_over_r(r, 1.0 / sqrt(a_rho)) - erf_over_r(r, rb));
+    if (atab) {
+      double v, dv;
+      hermite_fn(atab, atab + natab, natab, adr, r, v, dv);
+      ra += v;
+      hermite_fn(atab + 2 * natab, atab + 3 * natab, natab, adr, r, v, dv);
+      pa += v;
+    } else {
+      ra += Z[I] * norm * exp(-a_rho * r2);
+      pa += Z[I] * (erf_over_r(r, 1.0 / sqrt(a_rho)) - erf_over_r(r, rb));
+    }
     vs += amp * exp(-(r / rg) * (r / rg));
   }
   rho_at[idx] = ra;
   phi_at[idx] = pa;
   v_short[idx] = vs;
+}
+
+// <n_I, n_J> of two tabulated neutral atoms at distance R (n = rho + b, b
+// the Gaussian smeared charge -Z of width rb, phi the potential of n):
+// 2 pi sum_k w_k r_k^2 n(r_k) sum_m u_m phi(d_km), d_km^2 = r_k^2 + R^2 -
+// 2 r_k R mu_m, over the table points (trapezoid weights w) and the
+// Gauss-Legendre nodes (mu, u).  One work-group per unordered pair i <= j;
+// pe[pair] = the pair's share of 1/2 sum over ordered pairs.
+__global__ __launch_bounds__(256) void k_pair_tab(int natoms, const double *__restrict__ xyz,
+                                                  double Z, double rb,
+                                                  const double *__restrict__ atab, int n,
+                                                  double dr, const double *__restrict__ gl,
+                                                  int nmu, double *__restrict__ pe) {
+  __shared__ double red[256];
+  int64_t p = blockIdx.x;
+  int i = 0;
+  while (p >= natoms - i) {
+    p -= natoms - i;
+    ++i;
+  }
+  const int j = i + (int)p;
+  const double dx = xyz[3 * i] - xyz[3 * j], dy = xyz[3 * i + 1] - xyz[3 * j + 1],
+               dz = xyz[3 * i + 2] - xyz[3 * j + 2];
+  const double R = sqrt(dx * dx + dy * dy + dz * dz);
+  const double bnorm = -Z / (pow(M_PI, 1.5) * rb * rb * rb);
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < n; k += 256) {
+    const double r = k * dr;
+    const double w = (k == 0 || k == n - 1) ? 0.5 * dr : dr;
+    const double nr = atab[k] + bnorm * exp(-(r / rb) * (r / rb));
+    double inner = 0.0;
+    for (int m = 0; m < nmu; ++m) {
+      const double d = sqrt(fmax(r * r + R * R - 2.0 * r * R * gl[m], 0.0));
+      double v, dv;
+      hermite_fn(atab + 2 * n, atab + 3 * n, n, dr, d, v, dv);
+      inner += gl[nmu + m] * v;
+    }
+    acc += w * r * r * nr * inner;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) pe[blockIdx.x] = (i == j ? 0.5 : 1.0) * 2.0 * M_PI * red[0];
+}
+
+// out[0] += sum of the n values in index order (one work-group)
+__global__ __launch_bounds__(256) void k_sum_fixed(int64_t n, const double *__restrict__ v,
+                                                   double *__restrict__ out) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int64_t k = threadIdx.x; k < n; k += 256) acc += v[k];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] += red[0];
+}
+
+// Gauss-Legendre nodes and weights on [-1, 1] (Newton iteration on the
+// Legendre recurrence): x[0..n), w[0..n)
+static void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  for (int i = 0; i < (n + 1) / 2; ++i) {
+    double z = cos(M_PI * (i + 0.75) / (n + 0.5)), pp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p1 = 1.0, p2 = 0.0;
+      for (int j = 1; j <= n; ++j) {
+        const double p3 = p2;
+        p2 = p1;
+        p1 = ((2.0 * j - 1.0) * z * p2 - (j - 1.0) * p3) / j;
+      }
+      pp = n * (z * p1 - p2) / (z * z - 1.0);
+      const double z1 = z;
+      z = z1 - p1 / pp;
+      if (fabs(z - z1) < 1e-16) break;
+    }
+    x[i] = -z;
+    x[n - 1 - i] = z;
+    w[i] = w[n - 1 - i] = 2.0 / ((1.0 - z * z) * pp * pp);
+  }
 }
 
 // <g_a, g_b>(R) for unit Gaussians with exponents a, b
@@ -95,10 +192,11 @@ __device__ inline double gauss_coulomb(double R, double a, double b) {
   return erf_over_r(R, 1.0 / mu);
 }
 
-// 1/2 sum_IJ <n_I, n_J> - E_self + dE_ZZ (one thread per ordered pair)
+// 1/2 sum_IJ <n_I, n_J> - E_self + dE_ZZ (one thread per ordered pair);
+// gauss_pairs = false leaves the <n_I, n_J> terms to k_pair_tab
 __global__ void k_const_energy(int natoms, const double *__restrict__ xyz,
                                const double *__restrict__ Z, double a_rho, double rb,
-                               double *__restrict__ out) {
+                               bool gauss_pairs, double *__restrict__ out) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= (int64_t)natoms * natoms) return;
   const int i = t / natoms, j = t % natoms;
@@ -106,9 +204,10 @@ __global__ void k_const_energy(int natoms, const double *__restrict__ xyz,
                dz = xyz[3 * i + 2] - xyz[3 * j + 2];
   const double R = sqrt(dx * dx + dy * dy + dz * dz);
   const double ab = 1.0 / (rb * rb);
-  double e = 0.5 * Z[i] * Z[j] *
-             (gauss_coulomb(R, a_rho, a_rho) - 2.0 * gauss_coulomb(R, a_rho, ab) +
-              gauss_coulomb(R, ab, ab));
+  double e = gauss_pairs ? 0.5 * Z[i] * Z[j] *
+                               (gauss_coulomb(R, a_rho, a_rho) - 2.0 * gauss_coulomb(R, a_rho, ab) +
+                                gauss_coulomb(R, ab, ab))
+                         : 0.0;
   if (i == j) e -= Z[i] * Z[i] / (sqrt(2.0 * M_PI) * rb);
   if (i < j) e += Z[i] * Z[j] * erfc(R / (sqrt(2.0) * rb)) / R;
   atomicAdd(out, e);
@@ -734,12 +833,31 @@ static efe_status scf_init(efe_ctx *c) {
   HIPCHK(c, hipMemsetAsync(s.Kdiag, 0, nn * 8, c->stream));
   HIPCHK(c, hipMemsetAsync(s.scal, 0, 256 * 8, c->stream));
   const MeshGeo g = mesh_geo(c);
-  k_atomic_fields<<<cdiv(nq, 256), 256, 0, c->stream>>>(g, c->d_xq1, c->natoms, c->d_xyz, c->d_Zs,
-                                                        c->rho_alpha, c->loc_rc, c->loc_amp,
-                                                        c->loc_rg, s.rho_at, s.phi_at, s.v_short);
+  const bool atab = c->natab > 0;
+  k_atomic_fields<<<cdiv(nq, 256), 256, 0, c->stream>>>(
+      g, c->d_xq1, c->natoms, c->d_xyz, c->d_Zs, c->rho_alpha, c->loc_rc, c->loc_amp, c->loc_rg,
+      atab ? c->d_atom_tab : nullptr, c->natab, c->atab_dr, s.rho_at, s.phi_at, s.v_short);
+  std::vector<double> glh;
+  double *dgl = nullptr, *dpe = nullptr;
   if (c->natoms)
     k_const_energy<<<cdiv((int64_t)c->natoms * c->natoms, 256), 256, 0, c->stream>>>(
-        c->natoms, c->d_xyz, c->d_Zs, c->rho_alpha, c->loc_rc, s.scal);
+        c->natoms, c->d_xyz, c->d_Zs, c->rho_alpha, c->loc_rc, !atab, s.scal);
+  if (c->natoms && atab) {
+    // pair energies of the tabulated atoms, summed in pair order
+    constexpr int NMU = 64;
+    std::vector<double> gx, gw;
+    gauss_legendre(NMU, gx, gw);
+    glh = gx;
+    glh.insert(glh.end(), gw.begin(), gw.end());
+    const int64_t npr = (int64_t)c->natoms * (c->natoms + 1) / 2;
+    if ((st = efe_ws(c, 35, (size_t)(2 * NMU + npr) * 8, (void **)&dgl))) return st;
+    dpe = dgl + 2 * NMU;
+    HIPCHK(c, hipMemcpyAsync(dgl, glh.data(), 2 * NMU * 8, hipMemcpyHostToDevice, c->stream));
+    k_pair_tab<<<(unsigned)npr, 256, 0, c->stream>>>(c->natoms, c->d_xyz, c->Z[0], c->loc_rc,
+                                                    c->d_atom_tab, c->natab, c->atab_dr, dgl, NMU,
+                                                    dpe);
+    k_sum_fixed<<<1, 256, 0, c->stream>>>(npr, dpe, s.scal);
+  }
   k_kdiag<<<cdiv(c->n_cells * c->nloc, 256), 256, 0, c->stream>>>(c->n_cells, c->nloc, c->d_c2g,
                                                                    c->d_K, s.Kdiag);
   k_kdiag_fix<<<cdiv(nn, 256), 256, 0, c->stream>>>(nn, c->d_minv, s.Kdiag);

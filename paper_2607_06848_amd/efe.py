@@ -39,7 +39,8 @@ class SystemDesc(ctypes.Structure):
                 ("enr_rcut", ctypes.c_double), ("enr_t", ctypes.c_double),
                 ("rho_alpha", ctypes.c_double), ("enr_tab_n", ctypes.c_int32),
                 ("enr_tab_dr", ctypes.c_double), ("enr_tab", c_double_p),
-                ("enr_tab_rc", ctypes.c_double * 3)]
+                ("enr_tab_rc", ctypes.c_double * 3), ("atom_tab_n", ctypes.c_int32),
+                ("atom_tab_dr", ctypes.c_double), ("atom_tab", c_double_p)]
 
 
 class ChebParams(ctypes.Structure):
@@ -100,7 +101,7 @@ _SIGS = {
     "efe_get_sizes": (ctypes.c_int32, [ctypes.c_void_p, c_int64_p]),
     "efe_radial_atom": (ctypes.c_int32, [ctypes.POINTER(SystemDesc), ctypes.c_int32,
                                          ctypes.POINTER(RadialParams), ctypes.c_void_p]
-                        + [ctypes.c_void_p] * 6 + [ctypes.POINTER(RadialReport)]),
+                        + [ctypes.c_void_p] * 7 + [ctypes.POINTER(RadialReport)]),
     "efe_enrichment_amplification": (ctypes.c_int32, [ctypes.c_void_p, c_double_p]),
     "efe_get_coupling": (ctypes.c_int32, [ctypes.c_void_p, c_int64_p, c_int64_p]),
     "efe_get_tables": (ctypes.c_int32, [ctypes.c_void_p, c_int32_p, c_int32_p, c_int32_p,
@@ -221,6 +222,14 @@ class Context:
             sd.enr_tab = self._tab.ctypes.data_as(c_double_p)
             for l in range(L_):
                 sd.enr_tab_rc[l] = float(tab["rc"][l])
+        atab = w.get("atom_table")
+        if atab is not None:
+            # rows rho, rho', phi, phi'
+            self._atab = np.ascontiguousarray(np.stack(
+                [np.asarray(atab[k][i], np.float64) for k in ("rho", "phi") for i in (0, 1)]))
+            sd.atom_tab_n = self._atab.shape[1]
+            sd.atom_tab_dr = float(atab["dr"])
+            sd.atom_tab = self._atab.ctypes.data_as(c_double_p)
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
         self.stream = stream
@@ -547,22 +556,25 @@ def radial_atom(w, n=2000, h=0.02, lmax=1, nstates=2, kT=500 * 3.166811563e-6, b
     rho = torch.zeros(n, **dev)
     r0 = torch.zeros(lmax + 1, **dev)
     tab = torch.zeros(2 * (lmax + 1), n + 1, **dev)
+    atab = torch.zeros(4, n + 1, **dev)
     rep = RadialReport()
     st = lib().efe_radial_atom(ctypes.byref(sd), int(atom), ctypes.byref(pr),
                                _stream(stream), _ptr(eps), _ptr(u), _ptr(occ),
-                               _ptr(rho), _ptr(r0), _ptr(tab), ctypes.byref(rep))
+                               _ptr(rho), _ptr(r0), _ptr(tab), _ptr(atab), ctypes.byref(rep))
     if st != 0:
         raise EFEError(st, lib().efe_last_error(None).decode())
     torch.cuda.synchronize()
     t = float(w.get("enr_t", 0.33))
     T = tab.cpu().numpy()
+    A = atab.cpu().numpy()
     R0 = r0.cpu().numpy()
     return dict(eps=eps.cpu().numpy().reshape(lmax + 1, nstates),
                 occ=occ.cpu().numpy().reshape(lmax + 1, nstates),
                 u=u.cpu().numpy().reshape(lmax + 1, nstates, n), rho=rho.cpu().numpy(), r0=R0,
                 iterations=rep.iterations, residual=rep.residual, mu=rep.mu,
                 table=dict(f=T[0::2], df=T[1::2], dr=float(h), r0=R0, rc=R0 * (1.0 + 1.0 / t),
-                           t=t))
+                           t=t),
+                atom_table=dict(rho=(A[0], A[1]), phi=(A[2], A[3]), dr=float(h)))
 
 
 def efe_setup_mesh(workload, stream=None):
