@@ -5,8 +5,6 @@
 // two-sided block Jacobi eigensolver for the projected N x N problem.
 #include <algorithm>
 #include <cmath>
-#include <numeric>
-#include <vector>
 
 #include "efe_internal.h"
 
@@ -457,7 +455,7 @@ __global__ __launch_bounds__(256) void k_jacobi_sub(int64_t np, const double *__
   }
   __syncthreads();
   for (int sw = 0; sw < max_sweeps; ++sw) {
-    // off-diagonal and total size of S
+    // off-diagonal size of S
     double off = 0.0;
     for (int e = t; e < J2 * J2; e += 256) {
       const double v = S[e / J2][e % J2];
