@@ -223,6 +223,9 @@ def time_to_scf(args, w, new_run, on_pass):
         torch.cuda.synchronize()
         t_scf = time.perf_counter() - t0
         ctx.close()
+        # the next run allocates its own block: free this one first
+        del V, lam, v0
+        torch.cuda.empty_cache()
         res[name] = {"seconds": t_scf, "steps": len(hist),
                      "filter_passes": sum(h["passes"] for h in hist), "E_Ha": hist[-1]["E"],
                      "converged": len(hist) > 1
