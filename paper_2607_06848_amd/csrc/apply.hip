@@ -19,7 +19,29 @@
 #include "efe_device.h"
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef double v2d __attribute__((ext_vector_type(2)));
 
+// Streams that a launch reads or writes once and that are far larger than the
+// caches (cell matrices, the recurrence blocks, Y of a colour pass, the
+// enrichment partial rows) go with the non-temporal hint, so that they do not
+// evict what is re-read through L2 (the gathered cell rows, the projector
+// support rows).  The hint changes cache policy only, not the values.
+template <typename T>
+__device__ inline T ld_nt(const T *p) {
+  return __builtin_nontemporal_load(p);
+}
+template <typename T>
+__device__ inline void st_nt(T v, T *p) {
+  __builtin_nontemporal_store(v, p);
+}
+__device__ inline double2 ld_nt2(const double *p) {
+  const v2d t = __builtin_nontemporal_load(reinterpret_cast<const v2d *>(p));
+  return make_double2(t.x, t.y);
+}
+__device__ inline void st_nt2(double2 v, double *p) {
+  const v2d t = {v.x, v.y};
+  __builtin_nontemporal_store(t, reinterpret_cast<v2d *>(p));
+}
 
 // value of v in lane l (l wave-uniform), for every lane: two readlanes
 __device__ inline double lane_bcast(double v, int l) {
@@ -310,7 +332,7 @@ void k_cell3(CellOps<T> a) {
 #pragma unroll
       for (int r = 0; r < RBW; ++r) {
         const int64_t rb = min(rbase + r, nrb - 1);
-        dst[s][r] = ap[(rb * rs + min(k0 + s, kmax)) * 64];
+        dst[s][r] = ld_nt(&ap[(rb * rs + min(k0 + s, kmax)) * 64]);
       }
   };
   auto compute = [&](int buf, const T (&src)[4][RBW]) {
@@ -358,14 +380,17 @@ void k_cell3(CellOps<T> a) {
 #pragma unroll
         for (int cb = 0; cb < CBM; ++cb) {
           const int col = cb * 16 + li;
-          if (cb < CB && col < ncols) yp[col] = (double)acc[r][cb][v];
+          if (cb < CB && col < ncols) st_nt((double)acc[r][cb][v], &yp[col]);
         }
       }
     }
     return;
   }
   // scatter: per row block, all reads of Y first, then all writes, so the
-  // reads overlap instead of each waiting for the one before
+  // reads overlap instead of each waiting for the one before; the wide tiles
+  // stream Y non-temporally (the narrow ones, whose rows are a 128-byte
+  // piece, measured slower that way)
+  constexpr bool YNT = CBM > 1;
 #pragma unroll
   for (int r = 0; r < RBW; ++r) {
     const int rb = rbase + r;
@@ -384,13 +409,20 @@ void k_cell3(CellOps<T> a) {
     for (int v = 0; v < 4; ++v) {
       double yv[CBM];
 #pragma unroll
-      for (int cb = 0; cb < CBM; ++cb)
-        yv[cb] = a.Y[node[v] * a.ldy + min(cb * 16 + li, ncols - 1)];
+      for (int cb = 0; cb < CBM; ++cb) {
+        const int64_t o = node[v] * a.ldy + min(cb * 16 + li, ncols - 1);
+        yv[cb] = YNT ? ld_nt(&a.Y[o]) : a.Y[o];
+      }
 #pragma unroll
       for (int cb = 0; cb < CBM; ++cb) {
         const int col = cb * 16 + li;
-        if (ok[v] && cb < CB && col < ncols)
-          a.Y[node[v] * a.ldy + col] = yv[cb] + a.alpha * (double)acc[r][cb][v];
+        if (ok[v] && cb < CB && col < ncols) {
+          const double y = yv[cb] + a.alpha * (double)acc[r][cb][v];
+          if (YNT)
+            st_nt(y, &a.Y[node[v] * a.ldy + col]);
+          else
+            a.Y[node[v] * a.ldy + col] = y;
+        }
       }
     }
   }
@@ -660,7 +692,7 @@ __global__ __launch_bounds__(256) void k_expand_init(int64_t n_nodes, int ncols,
   // aligned arrays), else element by element
   auto ld2 = [&](const double *p, int q) -> double2 {
     const int64_t o = rowo + c0[q];
-    if (vec && two[q]) return *reinterpret_cast<const double2 *>(p + o);
+    if (vec && two[q]) return ld_nt2(p + o);
     double2 r;
     r.x = has[q] ? p[o] : 0.0;
     r.y = two[q] ? p[o + 1] : 0.0;
@@ -713,7 +745,7 @@ __global__ __launch_bounds__(256) void k_expand_init(int64_t n_nodes, int ncols,
     if (!inner) v.x = v.y = 0.0;
     const int64_t o = rowo + c0[q];
     if (vec && two[q]) {
-      *reinterpret_cast<double2 *>(Y + o) = v;
+      st_nt2(v, Y + o);
     } else {
       Y[o] = v.x;
       if (two[q]) Y[o + 1] = v.y;
@@ -746,7 +778,7 @@ __global__ __launch_bounds__(576) void k_enr_reduce(int nf, int ncols,
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int64_t cp = __builtin_amdgcn_readlane(cpv, min(i + j, cnt - 1));
-        v[j] = Yp[((int64_t)nf * cp + k) * ldp + colc];
+        v[j] = ld_nt(&Yp[((int64_t)nf * cp + k) * ldp + colc]);
       }
 #pragma unroll
       for (int j = 0; j < 4; ++j)
